@@ -1,0 +1,65 @@
+"""Planted mistakes in the oracle (on the CPU) must be caught by its pins.
+
+Each case patches one plausible slip into the oracle (a flipped sign, a
+transposed index, a dropped conjugate, a missing normalisation, a wrong
+kinetic factor, a wrong CG step) and checks that at least one pin test
+then fails."""
+import numpy as np
+import pytest
+
+from oracle import basis, dft, hamiltonian as ham, solvers
+
+import test_oracle_dft as tdft
+import test_oracle_hamiltonian as tham
+import test_oracle_solvers as tsol
+
+
+def _fails(fn, *a):
+    try:
+        fn(*a)
+    except (AssertionError, np.linalg.LinAlgError, FloatingPointError):
+        return True
+    return False
+
+
+def test_flipped_dft_sign_is_caught(monkeypatch):
+    orig = dft.dft_matrix
+    monkeypatch.setattr(dft, "dft_matrix", lambda n, sign: orig(n, -sign))
+    assert _fails(tdft.test_inverse_of_delta_is_plane_wave, (3, 4, 5))
+
+
+def test_missing_forward_normalisation_is_caught(monkeypatch):
+    orig = dft.forward
+    monkeypatch.setattr(dft, "forward", lambda f: orig(f) * np.asarray(f).size)
+    assert _fails(tdft.test_forward_of_plane_wave_is_unit_delta, (3, 4, 5))
+
+
+def test_transposed_local_index_is_caught(monkeypatch):
+    orig = ham.local_matrix
+    monkeypatch.setattr(ham, "local_matrix", lambda m, fft, vt: orig(m, fft, vt).T)
+    assert _fails(tham.test_single_complex_fourier_component)
+
+
+def test_dropped_projector_conjugate_is_caught(monkeypatch):
+    monkeypatch.setattr(ham, "nonlocal_matrix", lambda beta, dij: beta.T @ dij @ beta)
+    assert _fails(tham.test_nonlocal_on_orthonormal_projectors)
+
+
+def test_transposed_d_is_caught(monkeypatch):
+    monkeypatch.setattr(ham, "nonlocal_matrix", lambda beta, dij: beta.T @ dij.T @ beta.conj())
+    assert _fails(tham.test_nonlocal_on_orthonormal_projectors)
+
+
+def test_wrong_kinetic_factor_is_caught(monkeypatch):
+    monkeypatch.setattr(basis, "kinetic", lambda q2: q2)
+    assert _fails(tham.test_free_electron_gamma_spectrum_closed_form)
+
+
+def test_wrong_cg_step_sign_is_caught(monkeypatch):
+    orig = solvers.pcg
+
+    def bad(apply_a, apply_minv, b, x0, thr, max_iter=60):
+        return orig(apply_a, apply_minv, -b, x0, thr, max_iter)
+
+    monkeypatch.setattr(solvers, "pcg", bad)
+    assert _fails(tsol.test_pcg_on_a_small_spd_system)
