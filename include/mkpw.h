@@ -1,0 +1,152 @@
+/* mkpw -- many-k plane-wave Hamiltonian on AMD Instinct MI355X (gfx950).
+ *
+ * C-ABI of the batched Kohn-Sham H|psi> of Gong & Dal Corso (CPC 2024,
+ * arXiv 2412.01695) and of the two solvers built on it.  One context holds
+ * one crystal (lattice, cutoff, FFT mesh, k-point list, local potential,
+ * projectors) on one GPU; every k-point of the list is processed in the
+ * same kernel launches (the paper's "many k" method, Sec. 3, Algorithms
+ * new_gpu and phonon_new).
+ *
+ * Conventions
+ *   Units: lengths bohr, energies Hartree, wavefunction cutoff in Ry; the
+ *   basis at k is every G with |k+G|^2 < ecutwfc_Ry bohr^-2 (Sec. 2.2.1).
+ *   Complex numbers are interleaved (re, im) pairs: complex128 = 2 doubles,
+ *   complex64 = 2 floats.
+ *   Wavefunction arrays are (nk, nvec, npwx) row-major; row (k, v) holds the
+ *   npw[k] coefficients in the library's plane-wave order (ascending
+ *   |k+G|^2, ties by Miller index (m1, m2, m3) lexicographically; see
+ *   pw_get_miller) followed by npwx - npw[k] padding entries that must be
+ *   zero on input and are written as zero on output.
+ *   Device pointers are HIP device memory owned by the caller (e.g. torch
+ *   tensors); the library never frees or reallocates them.  All device work
+ *   is ordered on the context's stream; calls return once the work is
+ *   enqueued unless stated otherwise.  Host pointers are read during the
+ *   call only.
+ *   Every call returns a pw_status; on error pw_last_error() holds a message
+ *   and the context is unchanged unless stated otherwise.  No exception
+ *   crosses the ABI.
+ */
+#ifndef MKPW_H
+#define MKPW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pw_ctx pw_ctx;
+
+typedef enum {
+  PW_OK = 0,
+  PW_EINVAL = -1,  /* invalid argument (message says which) */
+  PW_ENOMEM = -2,  /* device allocation failed or HBM budget exceeded */
+  PW_EDEVICE = -3, /* HIP runtime error */
+  PW_ENOCONV = -4, /* solver stopped at max_iter; results and flags written */
+  PW_ESTATE = -5   /* call out of order (e.g. h_psi before set_vloc) */
+} pw_status;
+
+typedef enum {
+  PW_FP64 = 0, /* complex128 H|psi>, FP64 everywhere */
+  PW_MIXED = 1 /* complex64 H|psi> with FP32 accumulation; solvers keep FP64
+                  Gram / Rayleigh-Ritz / CG scalars and refine in FP64 */
+} pw_prec;
+
+/* Create a context on HIP device `hip_device`, ordering its work on
+ * `hip_stream` (a hipStream_t; NULL = a stream owned by the context, created
+ * with default priority).  hip_device = -1 makes a host-only context that
+ * can build and report the plane-wave basis but runs no device work (every
+ * device call then returns PW_ESTATE).  On success *out owns the context. */
+pw_status pw_create(pw_ctx** out, int hip_device, void* hip_stream);
+
+/* Free the context and every device buffer it owns.  NULL is a no-op. */
+void pw_destroy(pw_ctx* ctx);
+
+/* Message of the last failed call on this context; never NULL. */
+const char* pw_last_error(const pw_ctx* ctx);
+
+/* Options: "hbm_budget_bytes" (0 = none; larger device workspaces fail with
+ * PW_ENOMEM, the paper's memgpu input of Sec. 5.1), "davidson_basis_factor"
+ * (maximum Davidson basis in units of nbnd, default 4, Sec. 5.3), "trace"
+ * (nonzero: synchronise and check after every launch). */
+pw_status pw_set_option(pw_ctx* ctx, const char* key, int64_t value);
+
+/* Direct lattice, rows a1, a2, a3 in bohr (host, 9 doubles).  Resets the
+ * basis, potential and projectors. */
+pw_status pw_set_lattice(pw_ctx* ctx, const double a[9]);
+
+/* Wavefunction cutoff (Ry) and FFT mesh N1, N2, N3 (host, 3 ints; all zero
+ * = smallest 2,3,5-smooth N_i >= 2 floor(2 sqrt(ecut) |a_i| / 2pi) + 1).
+ * Sec. 4 requires the mesh to hold every G - G'; this library checks the
+ * weaker condition it needs, that each k's sphere fits the mesh without
+ * two plane waves sharing a mesh point (else PW_EINVAL). */
+pw_status pw_set_cutoff(pw_ctx* ctx, double ecutwfc_ry, const int fft[3]);
+
+/* k-point list: nk Cartesian vectors (host, nk*3 doubles, bohr^-1).  Builds
+ * the plane-wave sphere of every k (Sec. 2.2.1) and the FFT-mesh maps of
+ * Sec. 4.  Writes npw[k] to npw_out (host, nk ints, may be NULL) and the
+ * row length npwx (max npw rounded up to 64) to npwx_out (may be NULL).
+ * Resets the projectors. */
+pw_status pw_set_kpoints(pw_ctx* ctx, int nk, const double* k_cart, int32_t* npw_out, int32_t* npwx_out);
+
+/* Miller indices of the plane waves of k-point ik in the library's order
+ * (host, npw[ik]*3 ints). */
+pw_status pw_get_miller(const pw_ctx* ctx, int ik, int32_t* miller);
+
+/* Local potential V_eff(r) on the FFT mesh (Sec. 2.2.2, Sec. 4): host
+ * array of N1*N2*N3 real doubles in Ha, C order (l3 fastest), point
+ * l = (l1, l2, l3) at r = sum_i l_i / N_i a_i. */
+pw_status pw_set_vloc(pw_ctx* ctx, const double* v_r);
+
+/* Nonlocal pseudopotential (Sec. 2.2.3): projector values beta_p(k+G)
+ * (host, complex128 (nk, nproj, npwx), library plane-wave order, padding
+ * ignored) and the coefficients D_pq (host, complex128 nproj x nproj,
+ * Hermitian to 1e-12 relative, else PW_EINVAL).  nproj = 0 removes the
+ * nonlocal term.  nproj <= 32. */
+pw_status pw_set_projectors(pw_ctx* ctx, int nproj, const void* beta, const void* dij);
+
+/* Hpsi = H psi for every k-point and band at once (Sec. 3, H application):
+ * kinetic (1/2)|k+G|^2 psi, local potential (scatter -> inverse 3D FFT ->
+ * V(r) -> forward 3D FFT with 1/N_r -> gather) and nonlocal
+ * sum_pq beta_p D_pq <beta_q|psi> (Eqs. lambdah, gamma, finalnl).
+ * psi and hpsi: device, (nk, nbnd, npwx); complex128 for PW_FP64,
+ * complex64 for PW_MIXED; they must not overlap. */
+pw_status pw_h_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* hpsi);
+
+/* Lowest nbnd eigenpairs of H at every k by block Davidson (Sec. 2.1),
+ * all k-points advancing together, each stopping on its own.
+ * psi: device complex128 (nk, nbnd, npwx): starting vectors in, eigenvectors
+ * out (orthonormal).  eig_ha: host (nk, nbnd) doubles, eigenvalues in Ha.
+ * A k-point is converged when every band's eigenvalue changed by less than
+ * tol_ry/2 Ha in the last iteration and its residual norm |H psi - e psi| is
+ * below max(1e-5, sqrt(tol_ry)) (so the eigenvalue error is of order
+ * residual^2 / gap).  iters, converged: host (nk) ints, may be NULL.
+ * PW_MIXED applies H in complex64 until convergence, then refines in FP64
+ * until the eigenvalues change by less than tol_ry/2 Ha.
+ * Returns PW_ENOCONV if some k did not converge within max_iter. */
+pw_status pw_davidson(pw_ctx* ctx, pw_prec prec, int nbnd, void* psi, double* eig_ha, double tol_ry,
+                int max_iter, int32_t* iters, int32_t* converged);
+
+/* Batched preconditioned CG (Sec. 2.4) for the DFPT linear systems
+ * (Eq. linear_system at q = 0 with S = I and the valence projector of
+ * Eq. projector):  (H - eps_{k,nu} + alpha_k P_v) x_{k,nu} = rhs_{k,nu},
+ * P_v = sum_{mu<nocc} |u_mu><u_mu|, one system per (k, nu), nu < nrhs.
+ * psi_occ: device complex128 (nk, nocc, npwx) orthonormal u.
+ * eps_ha: host (nk, nrhs) doubles.  alpha_ha: host (nk) doubles, > 0.
+ * rhs: device complex128 (nk, nrhs, npwx).  dpsi: device complex128
+ * (nk, nrhs, npwx): initial guess in, solution out.
+ * Preconditioner M_GG = max(1, (|k+G|^2/2) / <psi_nu|T|psi_nu>) with psi_nu
+ * = psi_occ row nu (nrhs <= nocc) (Sec. 2.4).  Each system stops when
+ * |rho| = |Re <M^-1 r|r>| < thr; converged systems are frozen.
+ * iters: host (nk*nrhs) ints, may be NULL.  PW_MIXED applies H in complex64
+ * while the residual update and all scalars stay FP64.
+ * Returns PW_ENOCONV if some system did not converge within max_iter. */
+pw_status pw_dfpt_cg(pw_ctx* ctx, pw_prec prec, int nocc, const void* psi_occ, const double* eps_ha,
+               const double* alpha_ha, int nrhs, const void* rhs, void* dpsi, double thr, int max_iter,
+               int32_t* iters);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MKPW_H */

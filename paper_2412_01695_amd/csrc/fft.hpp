@@ -1,0 +1,221 @@
+// In-register mixed-radix (2, 3, 4, 5) complex FFT for one thread.
+//
+// The 3D transform of the paper (Sec. 4, Eqs. zfft, yfft, xfft, fwFFT) is a
+// sequence of 1D transforms of length N_i along each axis.  Here every 1D
+// line is held by one work-item in registers and transformed with a fully
+// unrolled decimation-in-time Cooley-Tukey recursion whose every index and
+// twiddle factor is a compile-time constant, so the data never leaves the
+// VGPRs and every twiddle is an immediate/SGPR operand.  Lines are exchanged
+// between axes through LDS by the calling kernel.
+//
+//   SIGN = +1 : X[l] = sum_m x[m] exp(+2 pi i l m / N)   (inverse, unnormalised)
+//   SIGN = -1 : X[m] = sum_l x[l] exp(-2 pi i l m / N)   (forward, 1/N applied elsewhere)
+//
+// Twiddles come from a constexpr sine/cosine (octant reduction on the exact
+// rational angle, then a Horner-evaluated Taylor series on [0, pi/4]); a host
+// test compares them with the C library.  Inputs that are known zeros (the
+// plane-wave sphere only fills the first W of N entries) are written as
+// literal zeros: built with -fno-signed-zeros the compiler folds every
+// operation on them away, which prunes the first radix stages for free.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <type_traits>
+#include <utility>
+
+namespace mkpw {
+
+template <class T>
+struct cplx {
+  T x, y;
+};
+
+template <class T>
+__host__ __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T>
+__host__ __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T>
+__host__ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// conj(a) * b
+template <class T>
+__host__ __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+template <class T>
+__host__ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// ---------------------------------------------------------------- compile-time loops
+
+template <class F, int... Is>
+__host__ __device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__host__ __device__ __forceinline__ void sfor(F&& f) {
+  sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ---------------------------------------------------------------- compile-time trigonometry
+
+namespace ct {
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// sin(x), cos(x) for 0 <= x <= pi/4 by Taylor series, Horner form, 13 terms
+constexpr double sin_small(double x) {
+  double x2 = x * x, r = 1.0;
+  for (int n = 25; n >= 3; n -= 2) r = 1.0 - x2 / double(n * (n - 1)) * r;
+  return x * r;
+}
+constexpr double cos_small(double x) {
+  double x2 = x * x, r = 1.0;
+  for (int n = 24; n >= 2; n -= 2) r = 1.0 - x2 / double(n * (n - 1)) * r;
+  return r;
+}
+
+constexpr double cos2pi(long p, long q);
+// sin(2 pi p / q) for any integers, q > 0
+constexpr double sin2pi(long p, long q) {
+  p %= q;
+  if (p < 0) p += q;
+  if (p == 0 || 2 * p == q) return 0.0;
+  if (2 * p > q) return -sin2pi(q - p, q);           // sin(2pi - a) = -sin a
+  if (4 * p > q) return sin2pi(q - 2 * p, 2 * q);    // sin(pi - a) = sin a   (p/q > 1/4)
+  if (4 * p == q) return 1.0;
+  if (8 * p > q) return cos2pi(q - 4 * p, 4 * q);    // sin a = cos(pi/2 - a)
+  return sin_small(2.0 * kPi * double(p) / double(q));
+}
+constexpr double cos2pi(long p, long q) {
+  p %= q;
+  if (p < 0) p += q;
+  if (p == 0) return 1.0;
+  if (2 * p == q) return -1.0;
+  if (4 * p == q || 4 * p == 3 * q) return 0.0;
+  if (2 * p > q) return cos2pi(q - p, q);            // cos(2pi - a) = cos a
+  if (4 * p > q) return -cos2pi(q - 2 * p, 2 * q);   // cos(pi - a) = -cos a
+  if (8 * p > q) return sin2pi(q - 4 * p, 4 * q);    // cos a = sin(pi/2 - a)
+  return cos_small(2.0 * kPi * double(p) / double(q));
+}
+}  // namespace ct
+
+// multiply v by exp(SIGN * 2 pi i J / N), trivial angles special-cased at compile time
+template <class T, long J, long N, int SIGN>
+__device__ __forceinline__ cplx<T> twiddle(cplx<T> v) {
+  constexpr long j = ((J % N) + N) % N;
+  if constexpr (j == 0) {
+    return v;
+  } else if constexpr (2 * j == N) {
+    return {-v.x, -v.y};
+  } else if constexpr (4 * j == N) {  // * (SIGN i)
+    return SIGN > 0 ? cplx<T>{-v.y, v.x} : cplx<T>{v.y, -v.x};
+  } else if constexpr (4 * j == 3 * N) {  // * (-SIGN i)
+    return SIGN > 0 ? cplx<T>{v.y, -v.x} : cplx<T>{-v.y, v.x};
+  } else {
+    constexpr T c = T(ct::cos2pi(j, N));
+    constexpr T s = T(SIGN * ct::sin2pi(j, N));
+    return {v.x * c - v.y * s, v.x * s + v.y * c};
+  }
+}
+
+// ---------------------------------------------------------------- butterflies (length R DFTs)
+
+template <class T, int SIGN>
+__device__ __forceinline__ void bfly2(cplx<T> (&a)[2]) {
+  cplx<T> t = a[0];
+  a[0] = cadd(t, a[1]);
+  a[1] = csub(t, a[1]);
+}
+
+template <class T, int SIGN>
+__device__ __forceinline__ void bfly4(cplx<T> (&a)[4]) {
+  cplx<T> s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+  cplx<T> s13 = cadd(a[1], a[3]), d13 = csub(a[1], a[3]);
+  // SIGN i * d13
+  cplx<T> r = SIGN > 0 ? cplx<T>{-d13.y, d13.x} : cplx<T>{d13.y, -d13.x};
+  a[0] = cadd(s02, s13);
+  a[2] = csub(s02, s13);
+  a[1] = cadd(d02, r);
+  a[3] = csub(d02, r);
+}
+
+// odd R: X_k = a0 + sum_j [(a_j + a_{R-j}) cos(2pi jk/R) + i SIGN (a_j - a_{R-j}) sin(2pi jk/R)]
+template <class T, int R, int SIGN>
+__device__ __forceinline__ void bfly_odd(cplx<T> (&a)[R]) {
+  constexpr int H = (R - 1) / 2;
+  cplx<T> s[H + 1], d[H + 1];
+  sfor<H>([&](auto jj) {
+    constexpr int j = decltype(jj)::value + 1;
+    s[j] = cadd(a[j], a[R - j]);
+    d[j] = csub(a[j], a[R - j]);
+  });
+  cplx<T> a0 = a[0];
+  cplx<T> x0 = a0;
+  sfor<H>([&](auto jj) { x0 = cadd(x0, s[decltype(jj)::value + 1]); });
+  sfor<H>([&](auto kk) {
+    constexpr int k = decltype(kk)::value + 1;
+    cplx<T> A = a0, B = {T(0), T(0)};
+    sfor<H>([&](auto jj) {
+      constexpr int j = decltype(jj)::value + 1;
+      constexpr T c = T(ct::cos2pi(long(j) * k, R));
+      constexpr T sn = T(SIGN * ct::sin2pi(long(j) * k, R));
+      A.x += s[j].x * c;
+      A.y += s[j].y * c;
+      B.x += d[j].x * sn;
+      B.y += d[j].y * sn;
+    });
+    // X_k = A + i B ; X_{R-k} = A - i B
+    a[k] = {A.x - B.y, A.y + B.x};
+    a[R - k] = {A.x + B.y, A.y - B.x};
+  });
+  a[0] = x0;
+}
+
+template <class T, int R, int SIGN>
+__device__ __forceinline__ void bfly(cplx<T> (&a)[R]) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    bfly2<T, SIGN>(a);
+  } else if constexpr (R == 4) {
+    bfly4<T, SIGN>(a);
+  } else {
+    static_assert(R % 2 == 1, "odd radix expected");
+    bfly_odd<T, R, SIGN>(a);
+  }
+}
+
+template <int N>
+constexpr int pick_radix() {
+  if constexpr (N == 1 || N == 2 || N == 3 || N == 4 || N == 5) return N;
+  else if constexpr (N % 4 == 0) return 4;
+  else if constexpr (N % 2 == 0) return 2;
+  else if constexpr (N % 3 == 0) return 3;
+  else if constexpr (N % 5 == 0) return 5;
+  else return N;  // prime: direct (odd) butterfly
+}
+
+// In-place length-N DFT of x (decimation in time, fully unrolled).
+template <class T, int N, int SIGN>
+__device__ __forceinline__ void fft(cplx<T> (&x)[N]) {
+  constexpr int R = pick_radix<N>();
+  if constexpr (R == N) {
+    bfly<T, N, SIGN>(x);
+  } else {
+    constexpr int M = N / R;
+    cplx<T> y[R][M];
+    sfor<R>([&](auto r) { sfor<M>([&](auto m) { y[r][m] = x[R * decltype(m)::value + decltype(r)::value]; }); });
+    sfor<R>([&](auto r) { fft<T, M, SIGN>(y[r]); });
+    sfor<M>([&](auto k1) {
+      constexpr int K1 = decltype(k1)::value;
+      cplx<T> t[R];
+      sfor<R>([&](auto r) {
+        constexpr int RR = decltype(r)::value;
+        t[RR] = twiddle<T, long(RR) * K1, N, SIGN>(y[RR][K1]);
+      });
+      bfly<T, R, SIGN>(t);
+      sfor<R>([&](auto k2) { x[K1 + M * decltype(k2)::value] = t[decltype(k2)::value]; });
+    });
+  }
+}
+
+}  // namespace mkpw

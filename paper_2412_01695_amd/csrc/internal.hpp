@@ -1,0 +1,104 @@
+// Library-internal definitions shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mkpw.h"
+
+namespace mkpw {
+
+// Per-k tables the H|psi> kernels read (device pointers) plus the launch shape.
+// The plane waves of k live in a W1 x W2 x W3 window of Miller indices
+// shifted to start at 0 (m' = m - min m); a "stick" is one (m1', m2') pair
+// that holds at least one plane wave.
+struct KTables {
+  int nk = 0, npwx = 0;
+  int n1 = 0, n2 = 0, n3 = 0;
+  int wx = 0, wy = 0, wz = 0;  // window extents (max over k)
+  int smax = 0;                // max sticks per k
+  const int* npw = nullptr;      // [nk]
+  const int* nstick = nullptr;   // [nk]
+  const int* gmap = nullptr;     // [nk * npwx]   (stick << 8) | m3'
+  const short* sof = nullptr;    // [nk * wx * wy] stick index of (m1', m2') or -1
+  const double* kin = nullptr;   // [nk * npwx]   |k+G|^2 / 2 (Ha)
+};
+
+// Which vectors to apply H to: for k, vectors [off[k], off[k] + cnt[k]) of a
+// (nk, kstride) array of rows of length npwx; cnt == nullptr means all k use
+// [0, nvec).
+struct VecSel {
+  int nvec = 0;             // grid extent in the band direction (max count)
+  long kstride = 0;         // elements between consecutive k
+  const int* off = nullptr; // [nk] or null
+  const int* cnt = nullptr; // [nk] or null
+};
+
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace mkpw
+
+struct pw_ctx {
+  int device = -1;
+  bool host_only = true;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // options
+  int64_t hbm_budget = 0;  // 0 = no budget
+  int64_t trace = 0;
+  int64_t dav_basis_factor = 4;
+
+  // crystal and basis
+  bool have_lattice = false, have_cutoff = false, have_k = false, have_v = false, have_proj = false;
+  double lat[9] = {0}, rec[9] = {0};
+  double ecut_ry = 0;
+  int fft[3] = {0, 0, 0};
+  int nk = 0, npwx = 0;
+  std::vector<double> kcart;
+  std::vector<int> npw, nstick;
+  std::vector<int32_t> miller;  // nk * npwx * 3
+  std::vector<double> kin;      // nk * npwx
+  std::vector<int> gmap;        // nk * npwx
+  std::vector<short> sof;       // nk * wx * wy
+  int wx = 0, wy = 0, wz = 0, smax = 0;
+
+  // device copies
+  std::vector<mkpw::DevMem> owned;
+  int* d_npw = nullptr;
+  int* d_nstick = nullptr;
+  int* d_gmap = nullptr;
+  short* d_sof = nullptr;
+  double* d_kin = nullptr;
+  double* d_v64 = nullptr;  // V(r) / N_r
+  float* d_v32 = nullptr;
+  int nproj = 0;
+  void* d_beta64 = nullptr;  // (nk, nproj, npwx) complex double
+  void* d_beta32 = nullptr;  // complex float
+  void* d_dij64 = nullptr;   // (nproj, nproj) complex double
+  void* d_dij32 = nullptr;
+  std::vector<double> dij;   // host copy, complex interleaved
+
+  mkpw::KTables tables() const;
+};
+
+namespace mkpw {
+
+pw_status set_err(pw_ctx* c, pw_status s, const std::string& msg);
+pw_status dev_alloc(pw_ctx* c, size_t bytes, void** out);
+void dev_free(pw_ctx* c, void* p);
+
+// H|psi> over the selected vectors (kernels in hpsi.hip). psi/hpsi are
+// complex double (prec = PW_FP64) or complex float (PW_MIXED).
+pw_status launch_hpsi(pw_ctx* c, pw_prec prec, const VecSel& sel, const void* psi, void* hpsi,
+                      hipStream_t stream);
+bool hpsi_supported(int n1, int n2, int n3);
+
+}  // namespace mkpw

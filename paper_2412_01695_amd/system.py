@@ -1,0 +1,72 @@
+"""Load a synthetic crystal into a library context (host-side marshalling).
+
+``System(cfg)`` creates a ``pw_ctx`` for one ``synth.Config``: lattice,
+cutoff and FFT mesh, the k-point list (the library builds the bases), the
+local potential on the mesh, and the projector values at every k+G of the
+library's own plane-wave order.  It also lays out wavefunction arrays in
+the library's (nk, nvec, npwx) format.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import mkpw, synth
+
+
+class System:
+    def __init__(self, cfg: synth.Config, device: int = 0, stream=None, vloc=None, with_projectors=True,
+                 dij=None):
+        self.cfg = cfg
+        self.device = device
+        self.ctx = mkpw.pw_create(device, stream)
+        try:
+            mkpw.pw_set_lattice(self.ctx, cfg.lat)
+            mkpw.pw_set_cutoff(self.ctx, cfg.ecut_ry, cfg.fft)
+            self.npw, self.npwx = mkpw.pw_set_kpoints(self.ctx, cfg.kpts)
+            self.miller = [mkpw.pw_get_miller(self.ctx, ik, int(n)) for ik, n in enumerate(self.npw)]
+            if device >= 0 or vloc is not None:
+                self.vloc = synth.vloc_grid(cfg) if vloc is None else np.asarray(vloc, dtype=np.float64)
+                mkpw.pw_set_vloc(self.ctx, self.vloc)
+            if with_projectors and cfg.nproj > 0:
+                beta = np.zeros((cfg.nk, cfg.nproj, self.npwx), dtype=np.complex128)
+                for ik in range(cfg.nk):
+                    q = synth.q_vectors(cfg, ik, self.miller[ik])
+                    beta[ik, :, :self.npw[ik]] = synth.beta_values(cfg, q)
+                self.beta = beta
+                mkpw.pw_set_projectors(self.ctx, beta, cfg.dij if dij is None else dij)
+        except Exception:
+            mkpw.pw_destroy(self.ctx)
+            self.ctx = None
+            raise
+
+    @property
+    def nk(self) -> int:
+        return self.cfg.nk
+
+    def close(self):
+        if self.ctx is not None:
+            mkpw.pw_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def layout(self, rows_by_k, nvec: int | None = None) -> np.ndarray:
+        """Pack per-k (nvec, npw_k) arrays into the (nk, nvec, npwx) complex128 layout."""
+        nvec = rows_by_k[0].shape[0] if nvec is None else nvec
+        out = np.zeros((self.nk, nvec, self.npwx), dtype=np.complex128)
+        for ik, r in enumerate(rows_by_k):
+            out[ik, :r.shape[0], :self.npw[ik]] = r
+        return out
+
+    def unpack(self, arr) -> list:
+        """(nk, nvec, npwx) -> list of (nvec, npw_k) arrays."""
+        a = np.asarray(arr)
+        return [a[ik, :, :self.npw[ik]] for ik in range(self.nk)]
+
+    def psi_guess(self, nbnd: int | None = None, seed: int | None = None) -> np.ndarray:
+        nbnd = self.cfg.nbnd if nbnd is None else nbnd
+        return self.layout([synth.psi_guess(self.cfg, ik, self.miller[ik], nbnd, seed) for ik in range(self.nk)])

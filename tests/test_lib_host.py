@@ -1,0 +1,111 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library loads, exports every function declared in include/mkpw.h, and
+a host-only context (hip_device = -1) builds the same plane-wave spheres as
+the oracle and rejects invalid input with the documented status codes."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import basis
+from paper_2412_01695_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mk():
+    from paper_2412_01695_amd import mkpw
+    return mkpw
+
+
+def test_exports_match_header(mk):
+    hdr = open(os.path.join(ROOT, "include", "mkpw.h")).read()
+    declared = sorted(set(re.findall(r"^\s*(?:pw_status|void|const char\*)\s+(pw_\w+)\(", hdr, re.M)))
+    assert declared == sorted(mk.EXPORTS)
+    import ctypes
+    lib = ctypes.CDLL(mk.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+def _host_ctx(mk, cfg):
+    ctx = mk.pw_create(-1, None)
+    mk.pw_set_lattice(ctx, cfg.lat)
+    mk.pw_set_cutoff(ctx, cfg.ecut_ry, cfg.fft)
+    return ctx
+
+
+@pytest.mark.parametrize("cid", [1, 2, 3, 4])
+def test_miller_sets_match_oracle(mk, cid):
+    cfg = synth.make_config(cid)
+    ctx = _host_ctx(mk, cfg)
+    try:
+        npw, npwx = mk.pw_set_kpoints(ctx, cfg.kpts)
+        assert npwx % 64 == 0 and npwx >= npw.max() and npwx - npw.max() < 64
+        for ik in range(0, cfg.nk, max(1, cfg.nk // 40)):
+            m = mk.pw_get_miller(ctx, ik, npw[ik])
+            mo, q2 = basis.sphere(cfg.lat, cfg.kpts[ik], cfg.ecut_ry)
+            assert npw[ik] == mo.shape[0]
+            assert {tuple(x) for x in m} == {tuple(x) for x in mo}
+            # library order: ascending |k+G|^2
+            q = synth.q_vectors(cfg, ik, m)
+            qq = np.einsum("ij,ij->i", q, q)
+            assert np.all(np.diff(qq) >= -1e-12)
+            # no plane wave within 1e-9 of the cutoff (no ambiguous membership)
+            assert np.min(np.abs(q2 - cfg.ecut_ry)) > 1e-9
+    finally:
+        mk.pw_destroy(ctx)
+
+
+def test_auto_fft_rule(mk):
+    cfg = synth.make_config(2)
+    ctx = mk.pw_create(-1, None)
+    mk.pw_set_lattice(ctx, cfg.lat)
+    mk.pw_set_cutoff(ctx, 30.0, (0, 0, 0))
+    npw, npwx = mk.pw_set_kpoints(ctx, cfg.kpts[:4])
+    assert npw.min() > 0
+    mk.pw_destroy(ctx)
+
+
+def test_error_paths(mk):
+    cfg = synth.make_config(1)
+    ctx = mk.pw_create(-1, None)
+    with pytest.raises(mk.PwError) as e:
+        mk.pw_set_cutoff(ctx, 15.0, (15, 15, 15))
+    assert e.value.status == mk.PW_ESTATE
+    with pytest.raises(mk.PwError) as e:
+        mk.pw_set_lattice(ctx, np.zeros(9))
+    assert e.value.status == mk.PW_EINVAL
+    mk.pw_set_lattice(ctx, cfg.lat)
+    with pytest.raises(mk.PwError) as e:
+        mk.pw_set_option(ctx, "no_such_option", 1)
+    assert e.value.status == mk.PW_EINVAL
+    # a mesh too small for the sphere
+    mk.pw_set_cutoff(ctx, 15.0, (6, 6, 6))
+    with pytest.raises(mk.PwError) as e:
+        mk.pw_set_kpoints(ctx, cfg.kpts)
+    assert e.value.status == mk.PW_EINVAL and "too small" in str(e.value)
+    mk.pw_set_cutoff(ctx, 15.0, (15, 15, 15))
+    npw, npwx = mk.pw_set_kpoints(ctx, cfg.kpts)
+    # non-Hermitian D
+    beta = np.zeros((cfg.nk, 4, npwx), dtype=np.complex128)
+    d = cfg.dij.copy()
+    d[0, 1] = 0.3
+    with pytest.raises(mk.PwError) as e:
+        mk.pw_set_projectors(ctx, beta, d)
+    assert e.value.status == mk.PW_EINVAL
+    mk.pw_set_projectors(ctx, beta, cfg.dij)
+    # a host-only context runs no device work
+    with pytest.raises(mk.PwError) as e:
+        mk.pw_h_psi(ctx, mk.PW_FP64, 4, 0, 0)
+    assert e.value.status == mk.PW_ESTATE
+    # non-finite potential
+    v = np.zeros(cfg.fft)
+    v[1, 2, 3] = np.nan
+    with pytest.raises(mk.PwError) as e:
+        mk.pw_set_vloc(ctx, v)
+    assert e.value.status == mk.PW_EINVAL
+    mk.pw_destroy(ctx)
