@@ -1,0 +1,188 @@
+"""Benchmark: batched H|psi> over many k-points on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config 2] [--no-cpu] [--solve]
+
+A step is one pw_h_psi over the whole batch of the workload (every k-point
+and band in one launch, inputs resident in HBM).  The default workload is
+the 512-k-point fcc cell (ecut 30 Ry, FFT 24^3, 20 bands, 8 projectors);
+value is its FP64 throughput in k-band H|psi> per second, and the same
+batch is timed in mixed precision (complex64, FP32 accumulation) beside it.
+The dominant kernel's roofline fraction is computed from the algorithmic
+flop count of the pruned FFT pipeline (see `algorithmic_work`) over its
+average launch time measured with HIP events on the launch stream.  The
+CPU baseline is the FP64 oracle (dense H_k psi) timed on this host.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (256 CU x 64 lanes x 2 x 2.4 GHz)
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); unpacked issue caps at 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_work(cfg, miller_by_k, nbnd):
+    """Flops and I/O bytes per k-band of one H|psi>, averaged over the batch.
+
+    Pruned FFT pair with 5 N log2 N flops per complex 1D transform of length
+    N: z on the S_k occupied sticks, y on the W1_k occupied x columns of all
+    N3 planes, x on all N2 N3 lines, each both ways; 2 flops per mesh point
+    for V(r) u(r); 4 per plane wave for the kinetic term; 8 npw nproj for each
+    of lambda = beta^H psi and beta gamma plus 8 nproj^2 for gamma = D lambda.
+    I/O bytes: psi in and H psi out (16 B per complex128 coefficient) plus
+    the projector row block and per-k maps shared by the k's bands."""
+    n1, n2, n3 = cfg.fft
+    f1 = lambda n: 5.0 * n * math.log2(n)
+    flops = 0.0
+    io = 0.0
+    for m in miller_by_k:
+        npw = m.shape[0]
+        s = len({(int(a), int(b)) for a, b, _ in m})
+        w1 = int(m[:, 0].max() - m[:, 0].min() + 1)
+        fft = 2 * (s * f1(n3) + w1 * n3 * f1(n2) + n2 * n3 * f1(n1))
+        flops += fft + 2.0 * n1 * n2 * n3 + 4.0 * npw + 16.0 * npw * cfg.nproj + 8.0 * cfg.nproj ** 2
+        io += 2 * 16.0 * npw + (16.0 * cfg.nproj * npw + 16.0 * npw) / nbnd
+    k = len(miller_by_k)
+    return flops / k, io / k
+
+
+def cpu_baseline(cfg, vloc, miller_by_k, min_seconds=10.0, max_rounds=3):
+    """The FP64 oracle (build H_k densely, multiply) over the whole batch,
+    repeated until about min_seconds of CPU work; k-band/s."""
+    from oracle import basis, hamiltonian as ham
+    from paper_2412_01695_amd import synth
+
+    def bfn(c, ik, m):
+        return synth.beta_values(c, synth.q_vectors(c, ik, m))
+
+    psis = []
+    for ik in range(cfg.nk):
+        m, _ = basis.sphere(cfg.lat, cfg.kpts[ik], cfg.ecut_ry)
+        psis.append(synth.psi_guess(cfg, ik, m))
+    rounds, t0 = 0, time.perf_counter()
+    while True:
+        ham.h_psi(cfg, vloc, bfn, psis)
+        rounds += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds or rounds >= max_rounds:
+            break
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": rounds * cfg.nk * cfg.nbnd / el, "unit": "k-band/s", "cores": cores, "kind": "oracle",
+            "sample": f"whole batch ({cfg.nk} k x {cfg.nbnd} bands) x {rounds} round(s), {el:.1f} s, "
+                      f"numpy/OpenBLAS threads over {cores} cores"}
+
+
+def time_hpsi(torch, mkpw, ctx, prec, nbnd, psi, hpsi, steps, warmup):
+    for _ in range(warmup):
+        mkpw.pw_h_psi(ctx, prec, nbnd, psi, hpsi)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()   # the context's stream (set by the caller)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        mkpw.pw_h_psi(ctx, prec, nbnd, psi, hpsi)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall * 1e3 / steps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this library runs on one GPU; the k-point list shards across GPUs "
+                                   "as independent pools, which this benchmark does not launch",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2412_01695_amd import mkpw, synth
+    from paper_2412_01695_amd.system import System
+
+    cfg = synth.make_config(args.config)
+    torch.cuda.set_device(0)
+    sysm = System(cfg, 0)
+    torch.cuda.set_stream(sysm.stream)
+    nbnd = cfg.nbnd
+    psi_h = sysm.psi_guess()
+    psi64 = torch.from_numpy(psi_h).cuda()
+    h64 = torch.empty_like(psi64)
+    psi32 = psi64.to(torch.complex64)
+    h32 = torch.empty_like(psi32)
+    nkb = cfg.nk * nbnd
+    flops_kb, io_kb = algorithmic_work(cfg, sysm.miller, nbnd)
+
+    out = {}
+    if args.only in ("fp64", "both"):
+        ms64, wall64 = time_hpsi(torch, mkpw, sysm.ctx, mkpw.PW_FP64, nbnd, psi64, h64, args.steps, args.warmup)
+        out["fp64"] = ms64
+    if args.only in ("mixed", "both"):
+        ms32, wall32 = time_hpsi(torch, mkpw, sysm.ctx, mkpw.PW_MIXED, nbnd, psi32, h32, args.steps, args.warmup)
+        out["mixed"] = ms32
+
+    key = "fp64" if "fp64" in out else "mixed"
+    ms = out[key]
+    value = nkb / (ms * 1e-3)
+    flops_launch = flops_kb * nkb
+    achieved_tf = flops_launch / (ms * 1e-3) / 1e12
+    res = {
+        "metric": "k-band H|psi>/s (FP64 vs mixed FP32) at 1e-6 Ry; p50/p99 solve latency",
+        "value": value,
+        "unit": "k-band/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if key == "fp64" else "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: fcc a=7.6 bohr, {len(cfg.tau)} atom(s), ecut {cfg.ecut_ry:g} Ry, "
+                               f"FFT {cfg.fft[0]}^3, {cfg.nk} k-points (npw {int(sysm.npw.min())}-"
+                               f"{int(sysm.npw.max())}), {nbnd} bands, {cfg.nproj} projectors; one pw_h_psi "
+                               f"over all {nkb} k-band rows per step",
+                   "global_batch": nkb, "parallelism": "single GPU, all k in one launch"},
+        "roofline": {"bound": "alu", "achieved": achieved_tf,
+                     "peak": PEAK_FP64_TFLOPS if key == "fp64" else PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": achieved_tf / (PEAK_FP64_TFLOPS if key == "fp64" else PEAK_FP32_TFLOPS),
+                     "traffic": None,
+                     "kernel": "hpsi_kernel", "flops_per_kband": flops_kb,
+                     "io_bytes_per_kband": io_kb,
+                     "hbm_io_GBs": io_kb * nkb / (ms * 1e-3) / 1e9},
+    }
+    if "mixed" in out and "fp64" in out:
+        res["mixed"] = {"value": nkb / (out["mixed"] * 1e-3), "ms_per_step": out["mixed"], "dtype": "c64",
+                        "speedup_vs_fp64": out["fp64"] / out["mixed"],
+                        "roofline_frac": flops_launch / (out["mixed"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(cfg, sysm.vloc, sysm.miller)
+    sysm.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -107,10 +107,12 @@ void free_kdata(pw_ctx* c) {
 
 void free_all(pw_ctx* c) {
   free_kdata(c);
-  for (void** p : {(void**)&c->d_v64, (void**)&c->d_v32, (void**)&c->d_dij64, (void**)&c->d_dij32}) {
+  for (void** p : {(void**)&c->d_v64, (void**)&c->d_v32, (void**)&c->d_dij64, (void**)&c->d_dij32,
+                   (void**)&c->d_vperm64, (void**)&c->d_vperm32}) {
     dev_free(c, *p);
     *p = nullptr;
   }
+  c->vperm_l3c64 = c->vperm_l3c32 = 0;
   c->have_v = false;
 }
 
@@ -410,6 +412,7 @@ pw_status pw_set_vloc(pw_ctx* c, const double* v) {
   dev_free(c, c->d_v32);
   c->d_v64 = nullptr;
   c->d_v32 = nullptr;
+  c->vperm_l3c64 = c->vperm_l3c32 = 0;  // permuted copies are rebuilt from the new potential
   c->have_v = false;
   pw_status s;
   if ((s = upload(c, v64.data(), nr, &c->d_v64)) != PW_OK) return s;

@@ -19,6 +19,7 @@
 // the paper's N_k x N_b full FFT meshes in global memory are never formed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "fft.hpp"
@@ -49,8 +50,8 @@ __global__ __launch_bounds__(kHpsiThreads) void hpsi_kernel(KTables t, VecSel se
                                                            const cplx<T>* __restrict__ dij,
                                                            const T* __restrict__ vr,
                                                            const cplx<T>* __restrict__ psi,
-                                                           cplx<T>* __restrict__ hpsi, int l3c, int per_xcd,
-                                                           int ntask) {
+                                                           cplx<T>* __restrict__ hpsi, int l3c, int ys,
+                                                           int per_xcd, int ntask) {
   // XCD-aware order: consecutive (k, band) tasks run on the same XCD (blocks
   // are dealt to the 8 XCDs round-robin), so a k-point's projectors and maps
   // are fetched into one L2.
@@ -72,12 +73,12 @@ __global__ __launch_bounds__(kHpsiThreads) void hpsi_kernel(KTables t, VecSel se
   const short* __restrict__ sof = t.sof + (long)ik * t.wx * t.wy;
   const double* __restrict__ kin = t.kin + (long)ik * npwx;
   const int wx = t.wx, wy = t.wy;
-  constexpr int ZS = N;  // stick row stride
+  constexpr int ZS = N | 1;  // stick row stride (odd: no LDS bank aliasing between sticks)
 
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* Z = reinterpret_cast<cplx<T>*>(smem);  // [smax][ZS]
-  cplx<T>* Y = Z + (size_t)t.smax * ZS;            // [l3c][N][WC]
-  cplx<T>* red = Y + (size_t)l3c * N * WC;         // [4][kProjChunk]
+  cplx<T>* Y = Z + (size_t)t.smax * ZS;            // [l3c][N][ys], ys odd >= wx
+  cplx<T>* red = Y + (size_t)l3c * N * ys;         // [4][kProjChunk]
   cplx<T>* gam = red + 4 * kProjChunk;             // [32]
   cplx<T>* lam = gam + 32;                         // [32]
 
@@ -144,57 +145,61 @@ __global__ __launch_bounds__(kHpsiThreads) void hpsi_kernel(KTables t, VecSel se
   }
   __syncthreads();
 
-  // ---- 3. slabs of z planes
+  // ---- 3. slabs of z planes.  V is stored permuted per slab so that the
+  //         x-line work-items of a slab read it contiguously: Vp[slab][l1][lc][l2].
   for (int l30 = 0; l30 < N; l30 += l3c) {
     const int nl = min(l3c, N - l30);
-    // inverse y on columns m1' < WC: W inputs (from the sticks) -> N outputs
-    for (int i = tid; i < WC * nl; i += kHpsiThreads) {
-      const int m1 = i % WC, lc = i / WC, l3 = l30 + lc;
+    // inverse y on the occupied columns m1' < wx: W inputs (from the sticks) -> N outputs
+    for (int i = tid; i < wx * nl; i += kHpsiThreads) {
+      const int m1 = i % wx, lc = i / wx, l3 = l30 + lc;
       cplx<T> v[N];
       sfor<N>([&](auto j) {
         constexpr int J = decltype(j)::value;
         v[J] = zero;
         if constexpr (J < WC) {
-          if (m1 < wx && J < wy) {
+          if (J < wy) {
             int s = sof[m1 * wy + J];
             if (s >= 0) v[J] = Z[s * ZS + l3];
           }
         }
       });
       fft<T, N, +1>(v);
-      cplx<T>* y = Y + (size_t)lc * N * WC + m1;
-      sfor<N>([&](auto l2) { y[decltype(l2)::value * WC] = v[decltype(l2)::value]; });
+      cplx<T>* y = Y + (size_t)lc * N * ys + m1;
+      sfor<N>([&](auto l2) { y[decltype(l2)::value * ys] = v[decltype(l2)::value]; });
     }
     __syncthreads();
     // x lines: W inputs -> N points -> * V/N_r -> forward -> W outputs
+    const T* vslab = vr + (size_t)l30 * N * N;
     for (int i = tid; i < N * nl; i += kHpsiThreads) {
-      const int l2 = i % N, lc = i / N, l3 = l30 + lc;
-      cplx<T>* y = Y + ((size_t)lc * N + l2) * WC;
+      const int l2 = i % N, lc = i / N;
+      cplx<T>* y = Y + ((size_t)lc * N + l2) * ys;
       cplx<T> v[N];
       sfor<N>([&](auto j) {
         constexpr int J = decltype(j)::value;
-        if constexpr (J < WC) v[J] = y[J];
+        if constexpr (J < WC) v[J] = (J < wx) ? y[J] : zero;
         else v[J] = zero;
       });
       fft<T, N, +1>(v);
-      const T* vv = vr + (size_t)l2 * N + l3;
+      const T* vv = vslab + i;
       sfor<N>([&](auto l1) {
         constexpr int L1 = decltype(l1)::value;
-        T f = vv[(size_t)L1 * N * N];
+        T f = vv[(size_t)L1 * nl * N];
         v[L1].x *= f;
         v[L1].y *= f;
       });
       fft<T, N, -1>(v);
-      sfor<WC>([&](auto j) { y[decltype(j)::value] = v[decltype(j)::value]; });
+      sfor<WC>([&](auto j) {
+        constexpr int J = decltype(j)::value;
+        if (J < wx) y[J] = v[J];
+      });
     }
     __syncthreads();
     // forward y: N inputs -> W outputs, back into the sticks
-    for (int i = tid; i < WC * nl; i += kHpsiThreads) {
-      const int m1 = i % WC, lc = i / WC, l3 = l30 + lc;
-      if (m1 >= wx) continue;
-      const cplx<T>* y = Y + (size_t)lc * N * WC + m1;
+    for (int i = tid; i < wx * nl; i += kHpsiThreads) {
+      const int m1 = i % wx, lc = i / wx, l3 = l30 + lc;
+      const cplx<T>* y = Y + (size_t)lc * N * ys + m1;
       cplx<T> v[N];
-      sfor<N>([&](auto l2) { v[decltype(l2)::value] = y[decltype(l2)::value * WC]; });
+      sfor<N>([&](auto l2) { v[decltype(l2)::value] = y[decltype(l2)::value * ys]; });
       fft<T, N, -1>(v);
       sfor<WC>([&](auto j) {
         constexpr int J = decltype(j)::value;
@@ -236,18 +241,36 @@ __global__ __launch_bounds__(kHpsiThreads) void hpsi_kernel(KTables t, VecSel se
 
 namespace {
 
+// V/N_r permuted for a slab width: Vp[l30 .. l30+nl)[l1][lc][l2] = V[l1][l2][l30+lc]
+template <class T>
+__global__ void permute_v_kernel(const T* __restrict__ v, T* __restrict__ vp, int n, int l3c) {
+  const long nr = (long)n * n * n;
+  for (long o = blockIdx.x * (long)blockDim.x + threadIdx.x; o < nr; o += (long)gridDim.x * blockDim.x) {
+    const long slab_len = (long)l3c * n * n;
+    const int l30 = (int)(o / slab_len) * l3c;
+    const int nl = min(l3c, n - l30);
+    long r = o - (long)l30 * n * n;
+    const int l1 = (int)(r / ((long)nl * n));
+    r -= (long)l1 * nl * n;
+    const int lc = (int)(r / n), l2 = (int)(r % n);
+    vp[o] = v[((long)l1 * n + l2) * n + l30 + lc];
+  }
+}
+
 template <class T, int N, int WC>
 pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st) {
   KTables t = c->tables();
   const size_t cs = sizeof(cplx<T>);
-  const size_t zbytes = (size_t)t.smax * N * cs;
+  const size_t zbytes = (size_t)t.smax * (N | 1) * cs;
   const size_t small = (4 * kProjChunk + 64) * cs;
-  const size_t plane = (size_t)N * WC * cs;
-  const size_t target = 64 * 1024;
+  const int ys = t.wx | 1;
+  const size_t plane = (size_t)N * ys * cs;
+  // slab width: enough x lines to occupy the workgroup, within an LDS share
+  // that leaves room for two workgroups per CU
+  const size_t share = 80 * 1024;
   const size_t limit = 160 * 1024;
-  long l3c = (long)((target > zbytes + small ? target - zbytes - small : 0) / plane);
-  if (l3c < 1) l3c = 1;
-  if (l3c > N) l3c = N;
+  long l3c = std::min<long>(N, std::max<long>(1, kHpsiThreads / N));
+  while (l3c > 1 && zbytes + small + (size_t)l3c * plane > share) --l3c;
   size_t lds = zbytes + small + (size_t)l3c * plane;
   if (lds > limit) return set_err(c, PW_EINVAL, "H|psi> working set does not fit in LDS for this mesh");
   auto kern = hpsi_kernel<T, N, WC>;
@@ -261,14 +284,25 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
   const long ntask = (long)t.nk * sel.nvec;
   if (ntask <= 0) return PW_OK;
   if (ntask > (1L << 30)) return set_err(c, PW_EINVAL, "too many (k, band) rows in one call");
+  const bool fp64 = sizeof(T) == 8;
+  // permuted potential for this slab width (built once per potential and width)
+  int& have = fp64 ? c->vperm_l3c64 : c->vperm_l3c32;
+  void*& vp = fp64 ? c->d_vperm64 : c->d_vperm32;
+  if (have != (int)l3c || !vp) {
+    if (!vp) {
+      pw_status s = dev_alloc(c, (size_t)N * N * N * sizeof(T), &vp);
+      if (s != PW_OK) return s;
+    }
+    const T* v = (const T*)(fp64 ? (const void*)c->d_v64 : (const void*)c->d_v32);
+    hipLaunchKernelGGL(permute_v_kernel<T>, dim3(64), dim3(256), 0, st, v, (T*)vp, N, (int)l3c);
+    have = (int)l3c;
+  }
   const int per_xcd = (int)((ntask + 7) / 8);
   const unsigned nblk = 8u * (unsigned)per_xcd;
-  const bool fp64 = sizeof(T) == 8;
   const cplx<T>* beta = (const cplx<T>*)(fp64 ? c->d_beta64 : c->d_beta32);
   const cplx<T>* dij = (const cplx<T>*)(fp64 ? c->d_dij64 : c->d_dij32);
-  const T* vr = (const T*)(fp64 ? (const void*)c->d_v64 : (const void*)c->d_v32);
   hipLaunchKernelGGL(kern, dim3(nblk), dim3(kHpsiThreads), lds, st, t, sel, c->have_proj ? c->nproj : 0, beta,
-                     dij, vr, (const cplx<T>*)psi, (cplx<T>*)hpsi, (int)l3c, per_xcd, (int)ntask);
+                     dij, (const T*)vp, (const cplx<T>*)psi, (cplx<T>*)hpsi, (int)l3c, ys, per_xcd, (int)ntask);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(c, PW_EDEVICE, std::string("h_psi launch: ") + hipGetErrorString(e));
   if (c->trace) {

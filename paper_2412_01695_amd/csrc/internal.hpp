@@ -79,6 +79,9 @@ struct pw_ctx {
   double* d_kin = nullptr;
   double* d_v64 = nullptr;  // V(r) / N_r
   float* d_v32 = nullptr;
+  void* d_vperm64 = nullptr;  // V/N_r permuted for the kernel's slab width
+  void* d_vperm32 = nullptr;
+  int vperm_l3c64 = 0, vperm_l3c32 = 0;
   int nproj = 0;
   void* d_beta64 = nullptr;  // (nk, nproj, npwx) complex double
   void* d_beta32 = nullptr;  // complex float

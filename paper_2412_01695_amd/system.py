@@ -18,7 +18,21 @@ class System:
                  dij=None):
         self.cfg = cfg
         self.device = device
-        self.ctx = mkpw.pw_create(device, stream)
+        self.stream = None
+        ptr = None
+        if device >= 0:
+            import torch
+            # the context orders its work on this torch stream (default priority);
+            # torch's default stream has handle 0, which the C-ABI reads as "no stream"
+            if stream is None:
+                self.stream = torch.cuda.Stream(device=device)
+            elif isinstance(stream, torch.cuda.Stream):
+                self.stream = stream
+            else:
+                self.stream = torch.cuda.ExternalStream(int(stream), device=device) if stream else \
+                    torch.cuda.Stream(device=device)
+            ptr = self.stream.cuda_stream
+        self.ctx = mkpw.pw_create(device, ptr)
         try:
             mkpw.pw_set_lattice(self.ctx, cfg.lat)
             mkpw.pw_set_cutoff(self.ctx, cfg.ecut_ry, cfg.fft)

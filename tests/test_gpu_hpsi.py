@@ -24,7 +24,7 @@ TOL32 = 2e-6
 def _system(cfg, **kw):
     torch = torch_cuda()
     from paper_2412_01695_amd.system import System
-    return torch, System(cfg, 0, stream_ptr(torch), **kw)
+    return torch, System(cfg, 0, **kw)
 
 
 def _run(torch, sysm, psi, prec):
