@@ -110,6 +110,9 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one 1 GiB device-to-device copy (a known-size "
+                         "reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; the k-point list shards across GPUs "
@@ -141,6 +144,15 @@ def main():
     if args.only in ("mixed", "both"):
         ms32, wall32 = time_hpsi(torch, mkpw, sysm.ctx, mkpw.PW_MIXED, nbnd, psi32, h32, args.steps, args.warmup)
         out["mixed"] = ms32
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     key = "fp64" if "fp64" in out else "mixed"
     ms = out[key]

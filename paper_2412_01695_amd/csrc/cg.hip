@@ -1,0 +1,318 @@
+// Batched preconditioned conjugate gradient for the DFPT linear systems
+// (Sec. 2.3 Eq. linear_system at q = 0 with S = I, the valence projector of
+// Eq. projector, and the CG recurrence of Sec. 2.4, Eqs. ax1 .. updatedold),
+// one system per (k-point, band), all of them advancing in the same launches
+// (Sec. 3, Algorithm phonon_new).  Converged systems are frozen.
+//
+//   A x = H x - eps_nu x + alpha_k U (U^H x),   U = occupied states at k
+//   r = A x - b;  loop:  d = M^-1 r;  rho = Re(d^H r);  stop if |rho| < thr;
+//                        (from the 2nd iteration) d += (rho/rho_old) d_old;
+//                        t = A d;  lambda = -Re(d^H r) / Re(d^H t);
+//                        x += lambda d;  r += lambda t;  d_old = d;  rho_old = rho
+//   M_GG = max(1, (|k+G|^2/2) / <u_nu|T|u_nu>)   (Sec. 2.4 preconditioner)
+// The paper keeps rho, gamma and lambda on the CPU; here every scalar stays
+// on the device and the host only reads the per-system "active" flags.
+// Mixed precision applies H in complex64 (everything else FP64) until
+// convergence, then recomputes r = A x - b with H in FP64 and continues: the
+// FP32 phase does the bulk of the work and the FP64 phase removes its error.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mkpw {
+
+using cd = cplx<double>;
+
+namespace {
+
+__device__ __forceinline__ double block_sum2(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+// T_nu = sum_G |k+G|^2/2 |u_nu(G)|^2 for nu < nrhs
+__global__ __launch_bounds__(256) void tkin_kernel(const cd* U, int nocc, const double* kin, const int* npw, int npwx,
+                                                   int nrhs, double* tk) {
+  const int k = blockIdx.y, nu = blockIdx.x;
+  __shared__ double red[4];
+  const cd* u = U + ((long)k * nocc + nu) * npwx;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < npw[k]; g += 256) s += kin[(long)k * npwx + g] * (u[g].x * u[g].x + u[g].y * u[g].y);
+  s = block_sum2(s, red);
+  if (threadIdx.x == 0) tk[(long)k * nrhs + nu] = s;
+}
+
+// W(k)[mu][nu] *= alpha_k
+__global__ void scale_w_kernel(cd* W, int n, const double* alpha) {
+  const int k = blockIdx.x;
+  const double a = alpha[k];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    cd w = W[(long)k * n + e];
+    W[(long)k * n + e] = {a * w.x, a * w.y};
+  }
+}
+
+// r = t - eps x - b  (t = H x + alpha U U^H x);  every system restarts as active
+__global__ __launch_bounds__(256) void init_resid_kernel(const cd* t, const cd* x, const cd* b, const double* eps,
+                                                         cd* r, int npwx, int* active, const int* npw, int nrhs) {
+  const long sys = blockIdx.x;
+  const int k = (int)(sys / nrhs);
+  const double e = eps[sys];
+  const long o = sys * npwx;
+  for (int g = threadIdx.x; g < npwx; g += 256) {
+    cd v = {0.0, 0.0};
+    if (g < npw[k]) v = {t[o + g].x - e * x[o + g].x - b[o + g].x, t[o + g].y - e * x[o + g].y - b[o + g].y};
+    r[o + g] = v;
+  }
+  if (threadIdx.x == 0) active[sys] = 1;
+}
+
+// d = M^-1 r, rho = Re(d^H r); convergence; gamma step from the 2nd iteration
+__global__ __launch_bounds__(256) void step1_kernel(const cd* r, cd* d, const cd* dold, const double* kin,
+                                                    const double* tk, const int* npw, int npwx, int nrhs, double* rho,
+                                                    double* rho_old, int* active, int first, double thr) {
+  const long sys = blockIdx.x;
+  if (!active[sys]) return;
+  const int k = (int)(sys / nrhs);
+  __shared__ double red[4];
+  const long o = sys * npwx;
+  const double tkin = tk[sys];
+  double s = 0.0;
+  for (int g = threadIdx.x; g < npw[k]; g += 256) {
+    double m = fmax(1.0, kin[(long)k * npwx + g] / tkin);
+    cd v = {r[o + g].x / m, r[o + g].y / m};
+    s += v.x * r[o + g].x + v.y * r[o + g].y;
+  }
+  s = block_sum2(s, red);
+  if (fabs(s) < thr) {
+    if (threadIdx.x == 0) {
+      active[sys] = 0;
+      rho[sys] = s;
+    }
+    return;
+  }
+  const double gam = first ? 0.0 : s / rho_old[sys];
+  for (int g = threadIdx.x; g < npwx; g += 256) {
+    cd v = {0.0, 0.0};
+    if (g < npw[k]) {
+      double m = fmax(1.0, kin[(long)k * npwx + g] / tkin);
+      v = {r[o + g].x / m, r[o + g].y / m};
+      if (!first) v = {v.x + gam * dold[o + g].x, v.y + gam * dold[o + g].y};
+    }
+    d[o + g] = v;
+  }
+  if (threadIdx.x == 0) rho[sys] = s;
+}
+
+// t -= eps d ; lambda = -Re(d^H r)/Re(d^H t) ; x += lambda d ; r += lambda t ; d_old = d ; rho_old = rho
+__global__ __launch_bounds__(256) void step2_kernel(cd* t, const cd* d, cd* dold, cd* x, cd* r, const double* eps,
+                                                    const int* npw, int npwx, int nrhs, const double* rho,
+                                                    double* rho_old, const int* active) {
+  const long sys = blockIdx.x;
+  if (!active[sys]) return;
+  const int k = (int)(sys / nrhs);
+  __shared__ double red[4];
+  const long o = sys * npwx;
+  const double e = eps[sys];
+  double dr = 0.0, dt = 0.0;
+  for (int g = threadIdx.x; g < npw[k]; g += 256) {
+    cd tv = {t[o + g].x - e * d[o + g].x, t[o + g].y - e * d[o + g].y};
+    t[o + g] = tv;
+    dr += d[o + g].x * r[o + g].x + d[o + g].y * r[o + g].y;
+    dt += d[o + g].x * tv.x + d[o + g].y * tv.y;
+  }
+  dr = block_sum2(dr, red);
+  dt = block_sum2(dt, red);
+  const double lam = -dr / dt;
+  for (int g = threadIdx.x; g < npw[k]; g += 256) {
+    cd dv = d[o + g], tv = t[o + g];
+    x[o + g] = {x[o + g].x + lam * dv.x, x[o + g].y + lam * dv.y};
+    r[o + g] = {r[o + g].x + lam * tv.x, r[o + g].y + lam * tv.y};
+    dold[o + g] = dv;
+  }
+  if (threadIdx.x == 0) rho_old[sys] = rho[sys];
+}
+
+struct Buf2 {
+  pw_ctx* c;
+  std::vector<void*> ptrs;
+  explicit Buf2(pw_ctx* cc) : c(cc) {}
+  ~Buf2() {
+    for (void* p : ptrs) dev_free(c, p);
+  }
+  template <class T>
+  pw_status get(size_t n, T** out) {
+    void* p = nullptr;
+    pw_status s = dev_alloc(c, n * sizeof(T), &p);
+    if (s != PW_OK) return s;
+    ptrs.push_back(p);
+    *out = (T*)p;
+    return PW_OK;
+  }
+};
+
+#define CTRY(x)                  \
+  do {                           \
+    pw_status s_ = (x);          \
+    if (s_ != PW_OK) return s_;  \
+  } while (0)
+
+#define CHIP(c, call)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      (void)hipGetLastError();                                                                 \
+      return set_err((c), PW_EDEVICE, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+    }                                                                                          \
+  } while (0)
+
+}  // namespace
+
+pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const double* eps_h, const double* alpha_h,
+                      int nrhs, const cd* b, cd* x, double thr, int max_iter, int32_t* iters_out) {
+  hipStream_t st = c->stream;
+  const int nk = c->nk, npwx = c->npwx;
+  const long nsys = (long)nk * nrhs;
+  const size_t nv = (size_t)nsys * npwx;
+  Buf2 bf(c);
+  cd *r, *d, *dold, *t, *W;
+  double *eps, *alpha, *rho, *rho_old, *tk;
+  int* active;
+  CTRY(bf.get(nv, &r));
+  CTRY(bf.get(nv, &d));
+  CTRY(bf.get(nv, &dold));
+  CTRY(bf.get(nv, &t));
+  CTRY(bf.get((size_t)nk * nocc * nrhs, &W));
+  CTRY(bf.get((size_t)nsys, &eps));
+  CTRY(bf.get((size_t)nk, &alpha));
+  CTRY(bf.get((size_t)nsys, &rho));
+  CTRY(bf.get((size_t)nsys, &rho_old));
+  CTRY(bf.get((size_t)nsys, &tk));
+  CTRY(bf.get((size_t)nsys, &active));
+  cplx<float>*v32 = nullptr, *t32 = nullptr;
+  if (prec == PW_MIXED) {
+    CTRY(bf.get(nv, &v32));
+    CTRY(bf.get(nv, &t32));
+  }
+  CHIP(c, hipMemcpyAsync(eps, eps_h, sizeof(double) * nsys, hipMemcpyHostToDevice, st));
+  CHIP(c, hipMemcpyAsync(alpha, alpha_h, sizeof(double) * nk, hipMemcpyHostToDevice, st));
+  CHIP(c, hipMemsetAsync(dold, 0, sizeof(cd) * nv, st));
+  CHIP(c, hipMemsetAsync(rho_old, 0, sizeof(double) * nsys, st));
+  hipLaunchKernelGGL(tkin_kernel, dim3(nrhs, nk), dim3(256), 0, st, U, nocc, c->d_kin, c->d_npw, npwx, nrhs, tk);
+  CTRY(check_launch(c, "tkin", st));
+
+  bool fp64_h = prec == PW_FP64;
+  // t = H v + alpha U (U^H v) for all systems
+  auto apply_a = [&](const cd* v) -> pw_status {
+    if (fp64_h) {
+      VecSel sel;
+      sel.nvec = nrhs;
+      sel.kstride = (long)nrhs * npwx;
+      CTRY(launch_hpsi(c, PW_FP64, sel, v, t, st));
+    } else {
+      CTRY(launch_to_c64(c, v, (long)nrhs * npwx, nullptr, v32, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
+      VecSel sel;
+      sel.nvec = nrhs;
+      sel.kstride = (long)nrhs * npwx;
+      CTRY(launch_hpsi(c, PW_MIXED, sel, v32, t32, st));
+      CTRY(launch_to_c128(c, t32, (long)nrhs * npwx, nullptr, t, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
+    }
+    GramArgs g;
+    g.A = U; g.a_kstride = (long)nocc * npwx; g.a_n = nocc;
+    g.B = v; g.b_kstride = (long)nrhs * npwx; g.b_n = nrhs;
+    g.ld = npwx; g.npw = c->d_npw;
+    g.C = W; g.c_kstride = (long)nocc * nrhs; g.ldc = nrhs;
+    CTRY(launch_gram(c, g, nocc, nrhs, st));
+    hipLaunchKernelGGL(scale_w_kernel, dim3(nk), dim3(256), 0, st, W, nocc * nrhs, alpha);
+    CTRY(check_launch(c, "scale_w", st));
+    if (nocc > 64) return set_err(c, PW_EINVAL, "nocc must be <= 64");
+    CombArgs m;
+    m.X = U; m.x_kstride = (long)nocc * npwx; m.x_n = nocc;
+    m.Y = t; m.y_kstride = (long)nrhs * npwx; m.y_n = nrhs;
+    m.ld = npwx; m.Cm = W; m.c_kstride = (long)nocc * nrhs; m.ldc = nrhs;
+    m.accumulate = 1;
+    CTRY(launch_combine(c, m, nocc, st));
+    return PW_OK;
+  };
+  auto restart = [&]() -> pw_status {
+    CTRY(apply_a(x));
+    hipLaunchKernelGGL(init_resid_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, x, b, eps, r, npwx, active,
+                       c->d_npw, nrhs);
+    return check_launch(c, "init_resid", st);
+  };
+
+  std::vector<int> act(nsys, 1), iters(nsys, 0);
+  CTRY(restart());
+  int first = 1;
+  bool ok = false;
+  int it_total = 0;
+  for (int it = 1; it <= max_iter; ++it) {
+    hipLaunchKernelGGL(step1_kernel, dim3((unsigned)nsys), dim3(256), 0, st, r, d, dold, c->d_kin, tk, c->d_npw,
+                       npwx, nrhs, rho, rho_old, active, first, thr);
+    CTRY(check_launch(c, "cg_step1", st));
+    CHIP(c, hipMemcpyAsync(act.data(), active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
+    CHIP(c, hipStreamSynchronize(st));
+    long n_act = 0;
+    for (long s = 0; s < nsys; ++s)
+      if (act[s]) {
+        ++n_act;
+        iters[s] = it_total + it;
+      }
+    if (n_act == 0) {
+      if (!fp64_h) {
+        // FP64 refinement: true residual with H in FP64, then continue
+        fp64_h = true;
+        it_total += it;
+        first = 1;
+        CTRY(restart());
+        it = 0;
+        continue;
+      }
+      ok = true;
+      break;
+    }
+    first = 0;
+    CTRY(apply_a(d));
+    hipLaunchKernelGGL(step2_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, d, dold, x, r, eps, c->d_npw, npwx,
+                       nrhs, rho, rho_old, active);
+    CTRY(check_launch(c, "cg_step2", st));
+  }
+  CHIP(c, hipStreamSynchronize(st));
+  if (iters_out)
+    for (long s = 0; s < nsys; ++s) iters_out[s] = iters[s];
+  if (!ok) return set_err(c, PW_ENOCONV, "CG: some systems did not converge");
+  return PW_OK;
+}
+
+}  // namespace mkpw
+
+extern "C" pw_status pw_dfpt_cg(pw_ctx* c, pw_prec prec, int nocc, const void* psi_occ, const double* eps_ha,
+                                const double* alpha_ha, int nrhs, const void* rhs, void* dpsi, double thr,
+                                int max_iter, int32_t* iters) {
+  using namespace mkpw;
+  if (!c) return PW_EINVAL;
+  if (c->host_only) return set_err(c, PW_ESTATE, "host-only context runs no device work");
+  if (!c->have_k || !c->have_v) return set_err(c, PW_ESTATE, "set k-points and potential before dfpt_cg");
+  if (prec != PW_FP64 && prec != PW_MIXED) return set_err(c, PW_EINVAL, "unknown precision");
+  if (!psi_occ || !eps_ha || !alpha_ha || !rhs || !dpsi) return set_err(c, PW_EINVAL, "null argument");
+  if (nocc < 1 || nocc > 64) return set_err(c, PW_EINVAL, "nocc must be in [1, 64]");
+  if (nrhs < 1 || nrhs > nocc) return set_err(c, PW_EINVAL, "nrhs must be in [1, nocc]");
+  if (!(thr > 0.0)) return set_err(c, PW_EINVAL, "thr must be positive");
+  if (max_iter < 1) return set_err(c, PW_EINVAL, "max_iter must be >= 1");
+  for (int k = 0; k < c->nk; ++k)
+    if (!(alpha_ha[k] > 0.0)) return set_err(c, PW_EINVAL, "alpha must be positive");
+  (void)hipSetDevice(c->device);
+  return dfpt_cg_run(c, prec, nocc, (const cplx<double>*)psi_occ, eps_ha, alpha_ha, nrhs, (const cplx<double>*)rhs,
+                     (cplx<double>*)dpsi, thr, max_iter, iters);
+}

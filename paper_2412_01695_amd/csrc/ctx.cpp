@@ -404,6 +404,9 @@ pw_status pw_set_vloc(pw_ctx* c, const double* v) {
   // the forward transform's 1/N_r (Eq. fwFFT) is folded into the potential
   std::vector<double> v64(nr);
   std::vector<float> v32(nr);
+  double vsum = 0.0;
+  for (size_t i = 0; i < nr; ++i) vsum += v[i];
+  c->v0 = vsum / (double)nr;
   for (size_t i = 0; i < nr; ++i) {
     v64[i] = v[i] / (double)nr;
     v32[i] = (float)v64[i];

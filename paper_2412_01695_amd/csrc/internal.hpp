@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/mkpw.h"
+#include "fft.hpp"
 
 namespace mkpw {
 
@@ -35,6 +36,56 @@ struct VecSel {
   long kstride = 0;         // elements between consecutive k
   const int* off = nullptr; // [nk] or null
   const int* cnt = nullptr; // [nk] or null
+};
+
+// C = alpha A^H B over row blocks: A rows [a_off, a_off + a_cnt) of a
+// (nk, *, ld) array, likewise B; C(k) is a ldc-strided matrix, written at
+// (c_roff + i, c_coff + j) and, with mirror, conj at (c_coff + j, c_roff + i).
+// Null per-k pointers mean the scalar defaults a_row/a_n/... for every k.
+struct GramArgs {
+  const cplx<double>* A = nullptr;
+  long a_kstride = 0;
+  const int* a_off = nullptr;
+  const int* a_cnt = nullptr;
+  int a_row = 0, a_n = 0;
+  const cplx<double>* B = nullptr;
+  long b_kstride = 0;
+  const int* b_off = nullptr;
+  const int* b_cnt = nullptr;
+  int b_row = 0, b_n = 0;
+  int ld = 0;
+  const int* npw = nullptr;
+  cplx<double>* C = nullptr;
+  long c_kstride = 0;
+  int ldc = 0;
+  const int* c_roff = nullptr;
+  const int* c_coff = nullptr;
+  int c_row = 0, c_col = 0;
+  double alpha = 1.0;
+  int mirror = 0;
+};
+
+// Y_j = [Y_j +] alpha sum_i X_i C(c_row + i, c_col + j) for j < y_cnt, i < x_cnt.
+struct CombArgs {
+  const cplx<double>* X = nullptr;
+  long x_kstride = 0;
+  const int* x_off = nullptr;
+  const int* x_cnt = nullptr;
+  int x_row = 0, x_n = 0;
+  cplx<double>* Y = nullptr;
+  long y_kstride = 0;
+  const int* y_off = nullptr;
+  const int* y_cnt = nullptr;
+  int y_row = 0, y_n = 0;
+  int ld = 0;
+  const cplx<double>* Cm = nullptr;
+  long c_kstride = 0;
+  int ldc = 0;
+  const int* c_roff = nullptr;
+  const int* c_coff = nullptr;
+  int c_row = 0, c_col = 0;
+  double alpha = 1.0;
+  int accumulate = 0;
 };
 
 struct DevMem {
@@ -77,6 +128,7 @@ struct pw_ctx {
   int* d_gmap = nullptr;
   short* d_sof = nullptr;
   double* d_kin = nullptr;
+  double v0 = 0.0;          // mean of V(r): its G = 0 Fourier coefficient (Ha)
   double* d_v64 = nullptr;  // V(r) / N_r
   float* d_v32 = nullptr;
   void* d_vperm64 = nullptr;  // V/N_r permuted for the kernel's slab width
@@ -103,5 +155,27 @@ void dev_free(pw_ctx* c, void* p);
 pw_status launch_hpsi(pw_ctx* c, pw_prec prec, const VecSel& sel, const void* psi, void* hpsi,
                       hipStream_t stream);
 bool hpsi_supported(int n1, int n2, int n3);
+
+pw_status check_launch(pw_ctx* c, const char* what, hipStream_t st);
+pw_status launch_gram(pw_ctx* c, const GramArgs& a, int ni_max, int nj_max, hipStream_t st);
+pw_status launch_combine(pw_ctx* c, const CombArgs& a, int ni_max, hipStream_t st);
+pw_status launch_trmm(pw_ctx* c, cplx<double>* Y, long y_kstride, const int* y_off, const int* y_cnt,
+                      const cplx<double>* M, long m_kstride, int ldm, hipStream_t st);
+pw_status launch_to_c64(pw_ctx* c, const cplx<double>* src, long s_kstride, const int* s_off, cplx<float>* dst,
+                        long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st);
+pw_status launch_to_c128(pw_ctx* c, const cplx<float>* src, long s_kstride, const int* s_off, cplx<double>* dst,
+                         long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st);
+
+// Hermitian eigensolver (cyclic parallel Jacobi, one workgroup per k, LDS):
+// for each k with n[k] > 0, the n x n matrix A(k) (lda-strided) -> the lowest
+// nev eigenvalues (ascending) into w[k*nev..] and their eigenvectors as the
+// columns of V(k) (n x nev, ldv-strided).  n <= 64.
+pw_status launch_heev(pw_ctx* c, const cplx<double>* A, long a_kstride, int lda, const int* n, int nmax, int nev,
+                      double* w, cplx<double>* V, long v_kstride, int ldv, hipStream_t st);
+// Cholesky of the Hermitian positive definite S(k) (n[k] x n[k], <= 32) and
+// M(k) = L^-H (upper triangular) so that Y M has orthonormal rows when
+// S = Y Y^H; info[k] = 0 on success, 1 when S is not numerically positive.
+pw_status launch_chol_inv(pw_ctx* c, const cplx<double>* S, long s_kstride, int lds, const int* n, cplx<double>* M,
+                          long m_kstride, int ldm, int* info, hipStream_t st);
 
 }  // namespace mkpw

@@ -1,0 +1,244 @@
+"""Davidson and DFPT-CG through the C-ABI on the GPU against the FP64 oracle.
+
+Davidson: eigenvalues within 1e-10 Ry (5e-11 Ha) of the dense diagonalisation
+in FP64, within 1e-6 Ry after the FP64 refinement of the mixed-precision
+solve; returned vectors orthonormal with small residuals.
+CG: the solution of (H - eps + alpha P_v) x = rhs within 1e-9 (relative) of
+the oracle's exact solve, with the oracle's eigenvectors as the valence
+states on both sides."""
+import numpy as np
+import pytest
+
+from oracle import hamiltonian as ham, solvers
+from paper_2412_01695_amd import synth
+
+from gpu_util import to_dev, torch_cuda
+from helpers import beta_fn, miller_map
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64_HA = 0.5e-10
+TOL_MIXED_HA = 0.5e-6
+
+
+def _system(cfg, **kw):
+    torch = torch_cuda()
+    from paper_2412_01695_amd.system import System
+    return torch, System(cfg, 0, **kw)
+
+
+def _oracle_eigs(cfg, s, ks, nbnd):
+    vt = ham.vtilde(s.vloc)
+    out = {}
+    for ik in ks:
+        kp = ham.KPoint(cfg, ik, vt, beta_fn)
+        out[ik] = np.linalg.eigvalsh(kp.h)[:nbnd]
+    return out
+
+
+def _davidson(torch, s, prec, tol_ry, max_iter=300, nbnd=None):
+    from paper_2412_01695_amd import mkpw
+    nbnd = s.cfg.nbnd if nbnd is None else nbnd
+    psi = to_dev(torch, s.psi_guess(nbnd))
+    st, eig, iters, conv = mkpw.pw_davidson(s.ctx, prec, nbnd, psi, s.nk, tol_ry, max_iter)
+    torch.cuda.synchronize()
+    return st, eig, iters, conv, psi
+
+
+def _check_vectors(torch, s, psi, eig, tol_res):
+    from paper_2412_01695_amd import mkpw
+    h = torch.empty_like(psi)
+    mkpw.pw_h_psi(s.ctx, mkpw.PW_FP64, eig.shape[1], psi, h)
+    torch.cuda.synchronize()
+    p = psi.cpu().numpy()
+    hp = h.cpu().numpy()
+    for ik in range(s.nk):
+        n = s.npw[ik]
+        g = p[ik, :, :n].conj() @ p[ik, :, :n].T
+        assert np.max(np.abs(g - np.eye(g.shape[0]))) < 1e-12
+        r = hp[ik, :, :n] - eig[ik][:, None] * p[ik, :, :n]
+        assert np.max(np.linalg.norm(r, axis=1)) < tol_res
+        assert np.all(p[ik, :, n:] == 0)
+
+
+def test_davidson_c1_fp64():
+    cfg = synth.make_config(1)
+    torch, s = _system(cfg)
+    st, eig, iters, conv, psi = _davidson(torch, s, 0, 1e-10)
+    assert st == 0 and conv.all()
+    ref = _oracle_eigs(cfg, s, range(cfg.nk), cfg.nbnd)
+    err = max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref)
+    print("C1 fp64 max |eig err| Ha", err, "iters", iters)
+    assert err < TOL_FP64_HA
+    _check_vectors(torch, s, psi, eig, 1e-5)
+
+
+def test_davidson_c2_subset_fp64_ragged():
+    cfg = synth.subset(synth.make_config(2), np.arange(0, 512, 16))
+    torch, s = _system(cfg)
+    st, eig, iters, conv, psi = _davidson(torch, s, 0, 1e-10)
+    assert st == 0 and conv.all()
+    ref = _oracle_eigs(cfg, s, range(cfg.nk), cfg.nbnd)
+    err = max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref)
+    print("C2 subset fp64 max |eig err| Ha", err, "iters", iters.min(), iters.max())
+    assert err < TOL_FP64_HA
+    _check_vectors(torch, s, psi, eig, 1e-5)
+
+
+@pytest.mark.parametrize("cid", [1, 4])
+def test_davidson_mixed_refined(cid):
+    cfg0 = synth.make_config(cid)
+    cfg = cfg0 if cid == 1 else synth.subset(cfg0, np.arange(0, cfg0.nk, 96))
+    torch, s = _system(cfg)
+    st, eig, iters, conv, psi = _davidson(torch, s, 1, 1e-6)
+    assert st == 0 and conv.all()
+    ref = _oracle_eigs(cfg, s, range(cfg.nk), cfg.nbnd)
+    err = max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref)
+    print(cid, "mixed max |eig err| Ha", err, "iters", iters.min(), iters.max())
+    assert err < TOL_MIXED_HA
+
+
+def test_davidson_c2_full_batch_sampled():
+    cfg = synth.make_config(2)
+    torch, s = _system(cfg)
+    st, eig, iters, conv, psi = _davidson(torch, s, 0, 1e-10)
+    assert st == 0 and conv.all()
+    ks = list(range(0, cfg.nk, 41)) + [cfg.nk - 1]
+    ref = _oracle_eigs(cfg, s, ks, cfg.nbnd)
+    err = max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref)
+    print("C2 full fp64 max |eig err| Ha", err, "iters", iters.min(), iters.max())
+    assert err < TOL_FP64_HA
+
+
+def test_davidson_free_electron_degenerate():
+    # V = 0, no projectors: eigenvalues are the sorted kinetic energies, with
+    # multiplets split across the band cut at some k
+    cfg = synth.make_config(1)
+    torch, s = _system(cfg, vloc=np.zeros(cfg.fft), with_projectors=False)
+    st, eig, iters, conv, psi = _davidson(torch, s, 0, 1e-10)
+    assert st == 0
+    for ik in range(cfg.nk):
+        q = synth.q_vectors(cfg, ik, s.miller[ik])
+        kin = np.sort(0.5 * np.einsum("ij,ij->i", q, q))[:cfg.nbnd]
+        np.testing.assert_allclose(eig[ik], kin, atol=TOL_FP64_HA)
+
+
+def test_davidson_small_basis_restarts():
+    from paper_2412_01695_amd import mkpw
+    cfg = synth.make_config(1)
+    torch, s = _system(cfg)
+    mkpw.pw_set_option(s.ctx, "davidson_basis_factor", 2)
+    st, eig, iters, conv, psi = _davidson(torch, s, 0, 1e-10)
+    assert st == 0 and conv.all()
+    ref = _oracle_eigs(cfg, s, range(cfg.nk), cfg.nbnd)
+    assert max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref) < TOL_FP64_HA
+
+
+def test_davidson_noconv_flags():
+    from paper_2412_01695_amd import mkpw
+    cfg = synth.make_config(1)
+    torch, s = _system(cfg)
+    st, eig, iters, conv, psi = _davidson(torch, s, 0, 1e-10, max_iter=1)
+    assert st == mkpw.PW_ENOCONV and not conv.all()
+    assert np.all(iters == 1)
+
+
+# ------------------------------------------------------------------------------ DFPT CG
+
+def _dfpt_case(cfg, s, nocc, nrhs):
+    """Oracle eigenvectors as u, eps, alpha, rhs per k, in library order."""
+    vt = ham.vtilde(s.vloc)
+    dvt = ham.vtilde(synth.dv_grid(cfg))
+    u_l = np.zeros((cfg.nk, nocc, s.npwx), complex)
+    rhs_l = np.zeros((cfg.nk, nrhs, s.npwx), complex)
+    eps = np.zeros((cfg.nk, nrhs))
+    alpha = np.zeros(cfg.nk)
+    x_ref = []
+    for ik in range(cfg.nk):
+        kp = ham.KPoint(cfg, ik, vt, beta_fn)
+        w, u = solvers.lowest_eigpairs(kp.h, nocc)
+        a = solvers.dfpt_alpha(w)
+        rhs = solvers.dfpt_rhs(ham.local_matrix(kp.miller, cfg.fft, dvt), u)
+        perm = miller_map(s.miller[ik], kp.miller)
+        n = s.npw[ik]
+        u_l[ik, :, :n] = u.T[:, perm]
+        rhs_l[ik, :, :n] = rhs.T[:nrhs, perm]
+        eps[ik] = w[:nrhs]
+        alpha[ik] = a
+        xs = []
+        for nu in range(nrhs):
+            xs.append(solvers.dfpt_solve_exact(solvers.dfpt_matrix(kp.h, u, w[nu], a), rhs[:, nu])[perm])
+        x_ref.append(np.array(xs))
+    return u_l, rhs_l, eps, alpha, x_ref
+
+
+# |rho| = |r^H M^-1 r| < 1e-24 puts the residual near 1e-12; with the smallest
+# gap of these systems (~6e-4 Ha) the solution error is then below ~1e-9 relative
+THR = 1e-24
+
+
+def _run_cg(torch, s, prec, u, rhs, eps, alpha, thr=THR, max_iter=1000):
+    from paper_2412_01695_amd import mkpw
+    du = to_dev(torch, u)
+    drhs = to_dev(torch, rhs)
+    dx = torch.zeros_like(drhs)
+    st, iters = mkpw.pw_dfpt_cg(s.ctx, prec, u.shape[1], du, eps, alpha, rhs.shape[1], drhs, dx, thr, max_iter)
+    torch.cuda.synchronize()
+    return st, iters, dx.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cg_c1_vs_exact(prec):
+    cfg = synth.make_config(1)
+    torch, s = _system(cfg)
+    nocc = 5
+    u, rhs, eps, alpha, x_ref = _dfpt_case(cfg, s, nocc, nocc)
+    st, iters, x = _run_cg(torch, s, prec, u, rhs, eps, alpha)
+    assert st == 0
+    worst = 0.0
+    for ik in range(cfg.nk):
+        n = s.npw[ik]
+        for nu in range(nocc):
+            ref = x_ref[ik][nu]
+            worst = max(worst, np.linalg.norm(x[ik, nu, :n] - ref) / np.linalg.norm(ref))
+        assert np.all(x[ik, :, n:] == 0)
+    print("CG C1 prec", prec, "worst rel err", worst, "iters", iters.min(), iters.max())
+    assert worst < 1e-9
+
+
+def test_cg_c3_subset():
+    cfg0 = synth.make_config(3)
+    cfg = synth.subset(cfg0, np.arange(0, cfg0.nk, 128))
+    torch, s = _system(cfg)
+    nocc = cfg0.extra["nocc"]
+    u, rhs, eps, alpha, x_ref = _dfpt_case(cfg, s, nocc, nocc)
+    vt = ham.vtilde(s.vloc)
+    for prec in (0, 1):
+        st, iters, x = _run_cg(torch, s, prec, u, rhs, eps, alpha)
+        assert st == 0
+        worst = max(np.linalg.norm(x[ik, nu, :s.npw[ik]] - x_ref[ik][nu]) / np.linalg.norm(x_ref[ik][nu])
+                    for ik in range(cfg.nk) for nu in range(nocc))
+        # true residual with the oracle's dense A (library order via Miller map)
+        for ik in (0, cfg.nk - 1):
+            kp = ham.KPoint(cfg, ik, vt, beta_fn)
+            perm = miller_map(s.miller[ik], kp.miller)
+            uo = np.zeros((kp.npw, nocc), complex)
+            uo[perm, :] = u[ik, :, :s.npw[ik]].T
+            for nu in (0, nocc - 1):
+                a = solvers.dfpt_matrix(kp.h, uo, eps[ik, nu], alpha[ik])
+                xo = np.zeros(kp.npw, complex)
+                xo[perm] = x[ik, nu, :s.npw[ik]]
+                bo = np.zeros(kp.npw, complex)
+                bo[perm] = rhs[ik, nu, :s.npw[ik]]
+                assert np.linalg.norm(a @ xo - bo) <= 1e-10 * np.linalg.norm(bo)
+        print("CG C3 subset prec", prec, "worst rel err", worst, "iters", iters.min(), iters.max())
+        assert worst < 1e-9
+
+
+def test_cg_noconv():
+    from paper_2412_01695_amd import mkpw
+    cfg = synth.make_config(1)
+    torch, s = _system(cfg)
+    u, rhs, eps, alpha, _ = _dfpt_case(cfg, s, 5, 5)
+    st, iters, x = _run_cg(torch, s, 0, u, rhs, eps, alpha, max_iter=2)
+    assert st == mkpw.PW_ENOCONV
