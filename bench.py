@@ -1,6 +1,7 @@
 """Benchmark: batched H|psi> over many k-points on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config 2] [--no-cpu] [--solve]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config 2] [--no-cpu]
+                    [--no-solve] [--serve-requests 200]
 
 A step is one pw_h_psi over the whole batch of the workload (every k-point
 and band in one launch, inputs resident in HBM).  The default workload is
@@ -11,7 +12,11 @@ The dominant kernel's roofline fraction is computed from the algorithmic
 flop count of the pruned FFT pipeline (see `algorithmic_work`) over its
 average launch time measured with HIP events on the launch stream.  The
 CPU baseline is the FP64 oracle (dense H_k psi) timed on this host.
-Prints one JSON line.
+Beside the step throughput it reports the Davidson time-to-solution of the
+same batch (FP64 to 1e-10 Ry and mixed precision refined to 1e-6 Ry, with
+the eigenvalue error against the oracle's dense diagonalisation on sampled
+k-points) and the p50/p99 latency of the continuous-batching server on a
+Poisson stream of Davidson requests.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -86,6 +91,51 @@ def cpu_baseline(cfg, vloc, miller_by_k, min_seconds=10.0, max_rounds=3):
                       f"numpy/OpenBLAS threads over {cores} cores"}
 
 
+def oracle_eig_error(cfg, vloc, miller_lib, eigs, nsample=8):
+    """max |eig - dense eig| (Ry) on sampled k-points, per solve in `eigs`."""
+    from oracle import hamiltonian as ham
+    from paper_2412_01695_amd import synth
+
+    def bfn(c, ik, m):
+        return synth.beta_values(c, synth.q_vectors(c, ik, m))
+
+    vt = ham.vtilde(vloc)
+    ks = np.unique(np.linspace(0, cfg.nk - 1, nsample).astype(int))
+    err = {name: 0.0 for name in eigs}
+    for ik in ks:
+        ref = np.linalg.eigvalsh(ham.KPoint(cfg, int(ik), vt, bfn).h)[:cfg.nbnd]
+        for name, e in eigs.items():
+            err[name] = max(err[name], float(np.max(np.abs(e[ik] - ref))) * 2.0)
+    return err, [int(k) for k in ks]
+
+
+def time_davidson(torch, mkpw, sysm, prec, tol_ry):
+    cfg = sysm.cfg
+    psi = torch.from_numpy(sysm.psi_guess()).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, eig, iters, conv = mkpw.pw_davidson(sysm.ctx, prec, cfg.nbnd, psi, cfg.nk, tol_ry, 300)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"seconds": dt, "status": int(st), "converged_k": int(conv.sum()), "iters_min": int(iters.min()),
+            "iters_max": int(iters.max()), "tol_ry": tol_ry}, eig
+
+
+def serving_sample(n, rate=20.0):
+    from paper_2412_01695_amd import serve
+    reqs = serve.make_requests(n, rate)
+    serve.prewarm(reqs)
+    srv = serve.Server(0, 8)
+    t = time.monotonic()
+    serve.replay(reqs, srv)
+    wall = time.monotonic() - t
+    srv.close()
+    out = serve.summarize(reqs, wall)
+    out["stream"] = (f"{n} Poisson arrivals at {rate:g}/s: nk U{{16..1024}}, ecut U[20,45] Ry, nbnd U{{8..32}}, "
+                     f"1-2 atoms; mixed precision refined to 1e-6 Ry; 8 slots, 64 GiB HBM budget")
+    return out
+
+
 def time_hpsi(torch, mkpw, ctx, prec, nbnd, psi, hpsi, steps, warmup):
     for _ in range(warmup):
         mkpw.pw_h_psi(ctx, prec, nbnd, psi, hpsi)
@@ -109,6 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one 1 GiB device-to-device copy (a known-size "
@@ -190,9 +242,23 @@ def main():
         res["mixed"] = {"value": nkb / (out["mixed"] * 1e-3), "ms_per_step": out["mixed"], "dtype": "c64",
                         "speedup_vs_fp64": out["fp64"] / out["mixed"],
                         "roofline_frac": flops_launch / (out["mixed"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+    eigs = {}
+    if not args.no_solve:
+        solve = {}
+        for name, prec, tol in (("fp64", mkpw.PW_FP64, 1e-10), ("mixed", mkpw.PW_MIXED, 1e-6)):
+            solve[name], eigs[name] = time_davidson(torch, mkpw, sysm, prec, tol)
+            solve[name]["kband_per_s"] = nkb / solve[name]["seconds"]
+        res["solve"] = solve
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(cfg, sysm.vloc, sysm.miller)
+        if eigs:
+            err, ks = oracle_eig_error(cfg, sysm.vloc, sysm.miller, eigs)
+            for name in eigs:
+                res["solve"][name]["max_eig_err_vs_oracle_ry"] = err[name]
+            res["solve"]["oracle_k_sample"] = ks
     sysm.close()
+    if args.serve_requests > 0:
+        res["serving"] = serving_sample(args.serve_requests)
     print(json.dumps(res))
 
 

@@ -90,7 +90,8 @@ pw_status pw_set_cutoff(pw_ctx* ctx, double ecutwfc_ry, const int fft[3]);
 pw_status pw_set_kpoints(pw_ctx* ctx, int nk, const double* k_cart, int32_t* npw_out, int32_t* npwx_out);
 
 /* Miller indices of the plane waves of k-point ik in the library's order
- * (host, npw[ik]*3 ints). */
+ * (host, npw[ik]*3 ints); ik = -1 writes every k-point's list, concatenated
+ * in k order (host, sum_k npw[k]*3 ints). */
 pw_status pw_get_miller(const pw_ctx* ctx, int ik, int32_t* miller);
 
 /* Local potential V_eff(r) on the FFT mesh (Sec. 2.2.2, Sec. 4): host
@@ -104,6 +105,14 @@ pw_status pw_set_vloc(pw_ctx* ctx, const double* v_r);
  * Hermitian to 1e-12 relative, else PW_EINVAL).  nproj = 0 removes the
  * nonlocal term.  nproj <= 32. */
 pw_status pw_set_projectors(pw_ctx* ctx, int nproj, const void* beta, const void* dij);
+
+/* Random starting vectors for pw_davidson, drawn on the device:
+ * psi(k, b, G) = (x + i y) / (1 + |k+G|^2/2), normalised per band, x and y
+ * two N(0, 1) values (Box-Muller) from the SplitMix64 finaliser chained over
+ * (seed, k, b, packed Miller index (m1+512)<<20 | (m2+512)<<10 | (m3+512));
+ * the value at a plane wave does not depend on the batch or the order.
+ * psi: device complex128 (nk, nbnd, npwx), padding written as zero. */
+pw_status pw_init_guess(pw_ctx* ctx, int nbnd, uint64_t seed, void* psi);
 
 /* Hpsi = H psi for every k-point and band at once (Sec. 3, H application):
  * kinetic (1/2)|k+G|^2 psi, local potential (scatter -> inverse 3D FFT ->

@@ -15,7 +15,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -40,11 +42,13 @@ pw_status dev_alloc(pw_ctx* c, size_t bytes, void** out) {
       return set_err(c, PW_ENOMEM, "HBM budget exceeded: need " + std::to_string(used + bytes) +
                                        " bytes, budget " + std::to_string(c->hbm_budget));
   }
+  // stream-ordered allocation: no device-wide synchronisation, so contexts on
+  // other streams (other requests) keep running while this one allocates/frees
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
+  hipError_t e = hipMallocAsync(&p, bytes, c->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    return set_err(c, PW_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    return set_err(c, PW_ENOMEM, std::string("hipMallocAsync failed: ") + hipGetErrorString(e));
   }
   c->owned.push_back({p, bytes});
   *out = p;
@@ -55,11 +59,39 @@ void dev_free(pw_ctx* c, void* p) {
   if (!p) return;
   for (size_t i = 0; i < c->owned.size(); ++i) {
     if (c->owned[i].p == p) {
-      (void)hipFree(p);
+      (void)hipFreeAsync(p, c->stream);
       c->owned.erase(c->owned.begin() + i);
       return;
     }
   }
+}
+
+pw_status ensure_lds_limit(pw_ctx* c, const void* kernel, size_t lds) {
+  // Raise a kernel's dynamic-LDS limit to the CU's 160 KiB once per process,
+  // under a lock and before the first launch of that kernel, so that no
+  // thread changes a kernel's attributes while another thread launches it.
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> limit;  // dynamic LDS allowed per kernel
+  if (lds <= 64 * 1024) return PW_OK;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = limit.find(kernel);
+  if (it == limit.end()) {
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, kernel);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(c, PW_EDEVICE, std::string("hipFuncGetAttributes: ") + hipGetErrorString(e));
+    }
+    const size_t dyn_max = 160 * 1024 - fa.sharedSizeBytes;  // the CU's LDS minus the kernel's static LDS
+    e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(c, PW_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
+    it = limit.emplace(kernel, dyn_max).first;
+  }
+  if (lds > it->second) return set_err(c, PW_EINVAL, "kernel LDS request above what a CU provides");
+  return PW_OK;
 }
 
 }  // namespace mkpw
@@ -96,7 +128,7 @@ namespace {
 
 void free_kdata(pw_ctx* c) {
   for (void** p : {(void**)&c->d_npw, (void**)&c->d_nstick, (void**)&c->d_gmap, (void**)&c->d_sof,
-                   (void**)&c->d_kin, (void**)&c->d_beta64, (void**)&c->d_beta32}) {
+                   (void**)&c->d_kin, (void**)&c->d_mkey, (void**)&c->d_beta64, (void**)&c->d_beta32}) {
     dev_free(c, *p);
     *p = nullptr;
   }
@@ -175,9 +207,9 @@ void pw_destroy(pw_ctx* c) {
   if (!c) return;
   if (!c->host_only) {
     (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    for (auto& m : c->owned) (void)hipFree(m.p);
+    for (auto& m : c->owned) (void)hipFreeAsync(m.p, c->stream);
     c->owned.clear();
+    (void)hipStreamSynchronize(c->stream);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
@@ -327,6 +359,10 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
                      "FFT mesh too small: the plane-wave sphere spans " + std::to_string(wmax[d]) +
                          " points along axis " + std::to_string(d + 1) + " but N = " + std::to_string(c->fft[d]));
   if (wmax[2] > 255) return set_err(c, PW_EINVAL, "sphere too wide along axis 3");
+  for (int ik = 0; ik < nk; ++ik)
+    for (auto& p : all[ik])
+      for (int d = 0; d < 3; ++d)
+        if (p.m[d] < -512 || p.m[d] > 511) return set_err(c, PW_EINVAL, "Miller index outside [-512, 511]");
 
   const int wx = wmax[0], wy = wmax[1], wz = wmax[2];
   c->nk = nk;
@@ -376,6 +412,12 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
     if ((s = upload(c, c->gmap.data(), c->gmap.size(), &c->d_gmap)) != PW_OK) return s;
     if ((s = upload(c, c->sof.data(), c->sof.size(), &c->d_sof)) != PW_OK) return s;
     if ((s = upload(c, c->kin.data(), c->kin.size(), &c->d_kin)) != PW_OK) return s;
+    std::vector<int> mkey((size_t)nk * npwx, 0);
+    for (size_t o = 0; o < mkey.size(); ++o) {
+      const int32_t* m = c->miller.data() + 3 * o;
+      mkey[o] = ((m[0] + 512) << 20) | ((m[1] + 512) << 10) | (m[2] + 512);
+    }
+    if ((s = upload(c, mkey.data(), mkey.size(), &c->d_mkey)) != PW_OK) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   c->have_k = true;
@@ -385,6 +427,14 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
 pw_status pw_get_miller(const pw_ctx* c, int ik, int32_t* miller) {
   if (!c || !miller) return PW_EINVAL;
   if (!c->have_k) return set_err(const_cast<pw_ctx*>(c), PW_ESTATE, "no k-points set");
+  if (ik == -1) {  // every k, concatenated
+    size_t o = 0;
+    for (int k = 0; k < c->nk; ++k) {
+      std::memcpy(miller + o, c->miller.data() + (size_t)k * c->npwx * 3, sizeof(int32_t) * 3 * c->npw[k]);
+      o += 3 * (size_t)c->npw[k];
+    }
+    return PW_OK;
+  }
   if (ik < 0 || ik >= c->nk) return set_err(const_cast<pw_ctx*>(c), PW_EINVAL, "k index out of range");
   std::memcpy(miller, c->miller.data() + (size_t)ik * c->npwx * 3, sizeof(int32_t) * 3 * c->npw[ik]);
   return PW_OK;

@@ -274,12 +274,9 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
   size_t lds = zbytes + small + (size_t)l3c * plane;
   if (lds > limit) return set_err(c, PW_EINVAL, "H|psi> working set does not fit in LDS for this mesh");
   auto kern = hpsi_kernel<T, N, WC>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return set_err(c, PW_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
-    }
+  {
+    pw_status s = ensure_lds_limit(c, (const void*)kern, lds);
+    if (s != PW_OK) return s;
   }
   const long ntask = (long)t.nk * sel.nvec;
   if (ntask <= 0) return PW_OK;

@@ -128,6 +128,7 @@ struct pw_ctx {
   int* d_gmap = nullptr;
   short* d_sof = nullptr;
   double* d_kin = nullptr;
+  int* d_mkey = nullptr;    // (nk, npwx) packed Miller index ((m1+512)<<20 | (m2+512)<<10 | (m3+512))
   double v0 = 0.0;          // mean of V(r): its G = 0 Fourier coefficient (Ha)
   double* d_v64 = nullptr;  // V(r) / N_r
   float* d_v32 = nullptr;
@@ -157,6 +158,8 @@ pw_status launch_hpsi(pw_ctx* c, pw_prec prec, const VecSel& sel, const void* ps
 bool hpsi_supported(int n1, int n2, int n3);
 
 pw_status check_launch(pw_ctx* c, const char* what, hipStream_t st);
+// thread-safe, once-per-kernel raise of the dynamic LDS limit (needed above 64 KiB)
+pw_status ensure_lds_limit(pw_ctx* c, const void* kernel, size_t lds);
 pw_status launch_gram(pw_ctx* c, const GramArgs& a, int ni_max, int nj_max, hipStream_t st);
 pw_status launch_combine(pw_ctx* c, const CombArgs& a, int ni_max, hipStream_t st);
 pw_status launch_trmm(pw_ctx* c, cplx<double>* Y, long y_kstride, const int* y_off, const int* y_cnt,

@@ -227,14 +227,9 @@ pw_status launch_heev(pw_ctx* c, const cd* A, long a_kstride, int lda, const int
                       cd* V, long v_kstride, int ldv, hipStream_t st) {
   if (nmax > kHeevMax) return set_err(c, PW_EINVAL, "reduced problem larger than 64");
   const size_t lds = 2 * (size_t)kHeevMax * kHeevLd * sizeof(cd);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)heev_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return set_err(c, PW_EDEVICE, std::string("hipFuncSetAttribute(heev): ") + hipGetErrorString(e));
-    }
-    attr_set = true;
+  {
+    pw_status s = ensure_lds_limit(c, (const void*)heev_kernel, lds);
+    if (s != PW_OK) return s;
   }
   hipLaunchKernelGGL(heev_kernel, dim3(c->nk), dim3(256), lds, st, A, a_kstride, lda, n, nev, w, V, v_kstride, ldv);
   return check_launch(c, "heev", st);

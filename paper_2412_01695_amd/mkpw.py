@@ -25,11 +25,21 @@ STATUS_NAMES = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EDEVICE", 
                 -5: "PW_ESTATE"}
 
 EXPORTS = ["pw_create", "pw_destroy", "pw_last_error", "pw_set_option", "pw_set_lattice", "pw_set_cutoff",
-           "pw_set_kpoints", "pw_get_miller", "pw_set_vloc", "pw_set_projectors", "pw_h_psi", "pw_davidson",
-           "pw_dfpt_cg"]
+           "pw_set_kpoints", "pw_get_miller", "pw_set_vloc", "pw_set_projectors", "pw_init_guess", "pw_h_psi",
+           "pw_davidson", "pw_dfpt_cg"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2412_01695_amd.build`")
+
+# PyTorch ships its own HIP/HSA runtime with the same SONAME (libamdhip64.so.7)
+# as the system ROCm the library is linked against.  Loading the library first
+# would map both runtimes into the process, and device memory and streams from
+# torch would then be used through a second, independent runtime.  Importing
+# torch first makes the library bind to the runtime torch already loaded.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:  # host-only use without torch: the system runtime is the only one
+    _torch = None
 _lib = C.CDLL(LIB_PATH)
 
 _vp, _i, _d, _i64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
@@ -45,6 +55,7 @@ _sig = {
     "pw_get_miller": (_i, [_vp, _i, _pi]),
     "pw_set_vloc": (_i, [_vp, _pd]),
     "pw_set_projectors": (_i, [_vp, _i, _vp, _vp]),
+    "pw_init_guess": (_i, [_vp, _i, C.c_uint64, _vp]),
     "pw_h_psi": (_i, [_vp, _i, _i, _vp, _vp]),
     "pw_davidson": (_i, [_vp, _i, _i, _vp, _pd, _d, _i, _pi, _pi]),
     "pw_dfpt_cg": (_i, [_vp, _i, _i, _vp, _pd, _pd, _i, _vp, _vp, _d, _i, _pi]),
@@ -134,6 +145,17 @@ def pw_get_miller(ctx, ik: int, npw: int):
     m = np.zeros((npw, 3), dtype=np.int32)
     _check(ctx, _lib.pw_get_miller(ctx, int(ik), m.ctypes.data_as(_pi)))
     return m
+
+
+def pw_get_miller_all(ctx, npw):
+    """Every k's Miller list, concatenated (sum(npw), 3)."""
+    m = np.zeros((int(np.sum(npw)), 3), dtype=np.int32)
+    _check(ctx, _lib.pw_get_miller(ctx, -1, m.ctypes.data_as(_pi)))
+    return m
+
+
+def pw_init_guess(ctx, nbnd: int, seed: int, psi):
+    return _check(ctx, _lib.pw_init_guess(ctx, int(nbnd), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(psi)))
 
 
 def pw_set_vloc(ctx, v_r):

@@ -220,37 +220,82 @@ def beta_values(cfg: Config, q: np.ndarray) -> np.ndarray:
     q = np.asarray(q, dtype=np.float64)
     q2 = np.einsum("ij,ij->i", q, q)
     out = np.empty((len(cfg.projectors), q.shape[0]), dtype=np.complex128)
+    radial, phase = {}, {}
     for p, pr in enumerate(cfg.projectors):
-        ph = np.exp(-1j * (q @ cfg.tau[pr.atom]))
-        radial = np.exp(-0.5 * q2 * pr.rc * pr.rc) / math.sqrt(cfg.omega)
-        if pr.l == 0:
-            out[p] = radial * ph
-        else:
-            out[p] = (-1j) * q[:, pr.alpha] * pr.rc * radial * ph
+        if pr.rc not in radial:
+            radial[pr.rc] = np.exp(-0.5 * q2 * pr.rc * pr.rc) / math.sqrt(cfg.omega)
+        if pr.atom not in phase:
+            t = cfg.tau[pr.atom]
+            phase[pr.atom] = None if not np.any(t) else np.exp(-1j * (q @ t))
+        f = radial[pr.rc] if pr.l == 0 else (-1j * pr.rc) * q[:, pr.alpha] * radial[pr.rc]
+        out[p] = f if phase[pr.atom] is None else f * phase[pr.atom]
     return out
+
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _splitmix64(x):
+    """SplitMix64 finaliser (Steele, Lea & Flood 2014; constants as published by
+    Vigna) applied elementwise to uint64 arrays (wrapping arithmetic)."""
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def _normal_pairs(seed, ik, band, miller):
+    """Two independent N(0, 1) draws per (seed, k, band, Miller index), from a
+    counter-based hash: the value at a plane wave does not depend on which other
+    plane waves, k-points or bands are drawn, nor on their order."""
+    m = np.asarray(miller, dtype=np.int64)
+    key = _splitmix64(np.uint64(seed) * np.ones(1, np.uint64))
+    key = _splitmix64(key ^ np.asarray(ik, dtype=np.uint64))
+    key = _splitmix64(key[..., None] ^ np.asarray(band, dtype=np.uint64)[None, :])   # (..., nbnd)
+    packed = ((m[..., 0] + 512) << 20) | ((m[..., 1] + 512) << 10) | (m[..., 2] + 512)
+    h1 = _splitmix64(key[..., :, None] ^ packed.astype(np.uint64)[..., None, :])
+    h2 = _splitmix64(h1)
+    u1 = 1.0 - (h1 >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)   # (0, 1]
+    u2 = (h2 >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)         # [0, 1)
+    r = np.sqrt(-2.0 * np.log(u1))                                                      # Box-Muller
+    return r * np.cos(2.0 * math.pi * u2), r * np.sin(2.0 * math.pi * u2)
 
 
 def psi_guess(cfg: Config, ik: int, miller: np.ndarray, nbnd: int | None = None,
               seed: int | None = None) -> np.ndarray:
     """Initial wavefunctions (nbnd, npw) complex128, normalised per band.
 
-    psi(G) = (x + i y) / (1 + |k+G|^2/2), x, y ~ N(0, 1) from
-    default_rng([seed, ik]); the draws follow the Miller-lexicographic order
-    of the given plane waves, so the value at a plane wave does not depend
-    on the order of `miller`."""
+    psi(G) = (x + i y) / (1 + |k+G|^2/2), x, y ~ N(0, 1) drawn by a
+    counter-based hash of (seed, k index, band, Miller index), so the value
+    at a plane wave does not depend on the order of `miller`."""
     nbnd = cfg.nbnd if nbnd is None else nbnd
     seed = cfg.seed if seed is None else seed
     miller = np.asarray(miller)
-    npw = miller.shape[0]
-    order = np.lexsort((miller[:, 2], miller[:, 1], miller[:, 0]))
-    rng = np.random.default_rng([seed, ik])
-    x = rng.standard_normal((nbnd, npw))
-    y = rng.standard_normal((nbnd, npw))
-    z = np.empty((nbnd, npw), dtype=np.complex128)
-    z[:, order] = x + 1j * y
+    x, y = _normal_pairs(seed, np.uint64(ik), np.arange(nbnd, dtype=np.uint64), miller)
+    z = (x + 1j * y).reshape(nbnd, miller.shape[0])
     q = q_vectors(cfg, ik, miller)
     z /= (1.0 + 0.5 * np.einsum("ij,ij->i", q, q))[None, :]
     z /= np.linalg.norm(z, axis=1, keepdims=True)
+    return z
+
+
+def psi_guess_all(cfg: Config, miller_by_k, npwx: int, nbnd: int | None = None,
+                  seed: int | None = None) -> np.ndarray:
+    """`psi_guess` for every k at once, in the (nk, nbnd, npwx) layout (zero padding)."""
+    nbnd = cfg.nbnd if nbnd is None else nbnd
+    seed = cfg.seed if seed is None else seed
+    nk = len(miller_by_k)
+    npw = np.array([m.shape[0] for m in miller_by_k])
+    mm = np.zeros((nk, npwx, 3), dtype=np.int64)
+    valid = np.arange(npwx)[None, :] < npw[:, None]
+    for ik, m in enumerate(miller_by_k):
+        mm[ik, :npw[ik]] = m
+    x, y = _normal_pairs(seed, np.arange(nk, dtype=np.uint64), np.arange(nbnd, dtype=np.uint64), mm)
+    z = (x + 1j * y) * valid[:, None, :]
+    q = cfg.kpts[:, None, :] + mm.astype(np.float64) @ reciprocal_rows(cfg.lat)
+    z /= (1.0 + 0.5 * np.einsum("kgi,kgi->kg", q, q))[:, None, :]
+    z /= np.linalg.norm(z, axis=2, keepdims=True)
     return z
 
 

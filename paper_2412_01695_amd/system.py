@@ -43,9 +43,13 @@ class System:
                 mkpw.pw_set_vloc(self.ctx, self.vloc)
             if with_projectors and cfg.nproj > 0:
                 beta = np.zeros((cfg.nk, cfg.nproj, self.npwx), dtype=np.complex128)
+                q = np.concatenate([synth.q_vectors(cfg, ik, m) for ik, m in enumerate(self.miller)])
+                ball = synth.beta_values(cfg, q)
+                o = 0
                 for ik in range(cfg.nk):
-                    q = synth.q_vectors(cfg, ik, self.miller[ik])
-                    beta[ik, :, :self.npw[ik]] = synth.beta_values(cfg, q)
+                    n = int(self.npw[ik])
+                    beta[ik, :, :n] = ball[:, o:o + n]
+                    o += n
                 self.beta = beta
                 mkpw.pw_set_projectors(self.ctx, beta, cfg.dij if dij is None else dij)
         except Exception:
@@ -82,5 +86,4 @@ class System:
         return [a[ik, :, :self.npw[ik]] for ik in range(self.nk)]
 
     def psi_guess(self, nbnd: int | None = None, seed: int | None = None) -> np.ndarray:
-        nbnd = self.cfg.nbnd if nbnd is None else nbnd
-        return self.layout([synth.psi_guess(self.cfg, ik, self.miller[ik], nbnd, seed) for ik in range(self.nk)])
+        return synth.psi_guess_all(self.cfg, self.miller, self.npwx, nbnd, seed)

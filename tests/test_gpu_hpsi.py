@@ -167,3 +167,17 @@ def test_repeatable_bitwise():
     a = _run(torch, s, psi, 0)
     b = _run(torch, s, psi, 0)
     assert np.array_equal(a, b)
+
+
+def test_device_initial_guess_matches_generator():
+    # pw_init_guess draws the same counter-based values as synth.psi_guess_all
+    from paper_2412_01695_amd import mkpw
+    cfg = synth.subset(synth.make_config(2), np.arange(0, 512, 9))
+    torch, s = _system(cfg)
+    d = torch.full((cfg.nk, cfg.nbnd, s.npwx), float("nan"), dtype=torch.complex128, device="cuda")
+    mkpw.pw_init_guess(s.ctx, cfg.nbnd, cfg.seed, d)
+    torch.cuda.synchronize()
+    ref = synth.psi_guess_all(cfg, s.miller, s.npwx)
+    np.testing.assert_allclose(d.cpu().numpy(), ref, atol=1e-13, rtol=0)
+    m = mkpw.pw_get_miller_all(s.ctx, s.npw)
+    assert np.array_equal(m, np.concatenate(s.miller))

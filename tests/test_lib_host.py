@@ -109,3 +109,15 @@ def test_error_paths(mk):
         mk.pw_set_vloc(ctx, v)
     assert e.value.status == mk.PW_EINVAL
     mk.pw_destroy(ctx)
+
+
+def test_single_hip_runtime_whatever_the_import_order():
+    # the binding must bind the library to torch's HIP runtime even when it is
+    # imported before torch; two runtimes in one process crash on first use
+    import subprocess
+    import sys
+    code = ("import paper_2412_01695_amd.mkpw, torch; "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
