@@ -206,6 +206,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    shapes = {"variant": mkpw.pw_get_option(sysm.ctx, "hpsi_variant_tuned"),
+              "slab": mkpw.pw_get_option(sysm.ctx, "hpsi_slab_tuned")}
     key = "fp64" if "fp64" in out else "mixed"
     ms = out[key]
     value = nkb / (ms * 1e-3)
@@ -234,7 +236,8 @@ def main():
                      "unit": "TFLOP/s",
                      "frac": achieved_tf / (PEAK_FP64_TFLOPS if key == "fp64" else PEAK_FP32_TFLOPS),
                      "traffic": None,
-                     "kernel": "hpsi_kernel", "flops_per_kband": flops_kb,
+                     "kernel": "hpsi_kernel" if shapes["variant"] != 2 else "hpsi_pair_kernel",
+                     "tuned_shape_last": shapes, "flops_per_kband": flops_kb,
                      "io_bytes_per_kband": io_kb,
                      "hbm_io_GBs": io_kb * nkb / (ms * 1e-3) / 1e9},
     }

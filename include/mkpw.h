@@ -68,8 +68,17 @@ const char* pw_last_error(const pw_ctx* ctx);
 /* Options: "hbm_budget_bytes" (0 = none; larger device workspaces fail with
  * PW_ENOMEM, the paper's memgpu input of Sec. 5.1), "davidson_basis_factor"
  * (maximum Davidson basis in units of nbnd, default 4, Sec. 5.3), "trace"
- * (nonzero: synchronise and check after every launch). */
+ * (nonzero: synchronise and check after every launch), "hpsi_variant"
+ * (0 = autotuned on first use, 1 = one work-item per FFT line, 2 = two lanes
+ * per line, 3 = two lanes per z and y line and one per x line; 2 and 3 need
+ * even meshes) and "hpsi_slab" (0 = autotuned, else the number of z planes
+ * transformed together). */
 pw_status pw_set_option(pw_ctx* ctx, const char* key, int64_t value);
+
+/* Read an option (the keys above), or "hpsi_variant_tuned" / "hpsi_slab_tuned"
+ * (the shape the autotuner chose on this context's last tuning, 0 if none),
+ * or "device_bytes" (device memory the context holds now). */
+pw_status pw_get_option(const pw_ctx* ctx, const char* key, int64_t* value);
 
 /* Direct lattice, rows a1, a2, a3 in bohr (host, 9 doubles).  Resets the
  * basis, potential and projectors. */

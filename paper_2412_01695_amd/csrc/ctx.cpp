@@ -231,8 +231,34 @@ pw_status pw_set_option(pw_ctx* c, const char* key, int64_t value) {
     c->dav_basis_factor = value;
   } else if (k == "trace") {
     c->trace = value;
+  } else if (k == "hpsi_variant") {
+    if (value < 0 || value > 3) return set_err(c, PW_EINVAL, "hpsi_variant must be 0, 1, 2 or 3");
+    c->hpsi_variant = value;
+  } else if (k == "hpsi_slab") {
+    if (value < 0 || value > 512) return set_err(c, PW_EINVAL, "hpsi_slab must be in [0, 512]");
+    c->hpsi_slab = value;
   } else {
     return set_err(c, PW_EINVAL, "unknown option '" + k + "'");
+  }
+  return PW_OK;
+}
+
+pw_status pw_get_option(const pw_ctx* c, const char* key, int64_t* value) {
+  if (!c || !key || !value) return PW_EINVAL;
+  std::string k(key);
+  if (k == "hbm_budget_bytes") *value = c->hbm_budget;
+  else if (k == "davidson_basis_factor") *value = c->dav_basis_factor;
+  else if (k == "trace") *value = c->trace;
+  else if (k == "hpsi_variant") *value = c->hpsi_variant;
+  else if (k == "hpsi_slab") *value = c->hpsi_slab;
+  else if (k == "hpsi_variant_tuned") *value = c->last_hpsi_variant;
+  else if (k == "hpsi_slab_tuned") *value = c->last_hpsi_slab;
+  else if (k == "device_bytes") {
+    int64_t b = 0;
+    for (auto& m : c->owned) b += (int64_t)m.bytes;
+    *value = b;
+  } else {
+    return set_err(const_cast<pw_ctx*>(c), PW_EINVAL, "unknown option '" + k + "'");
   }
   return PW_OK;
 }

@@ -218,4 +218,75 @@ __device__ __forceinline__ void fft(cplx<T> (&x)[N]) {
   }
 }
 
+// ---------------------------------------------------------------- lane-pair transforms
+//
+// A length-N line (N = 2M) shared by two adjacent lanes of a wavefront:
+//  * pair_inverse: one radix-2 decimation-in-frequency step, after which lane p
+//    holds h[j] = X[2j + p] (j < M) -- X[2j] is the M-point DFT of
+//    x[m] + x[m+M], X[2j+1] that of (x[m] - x[m+M]) w^m -- so the two lanes
+//    need no exchange;
+//  * pair_forward: lane r holds u[j] = x[2j + r] (exactly what pair_inverse
+//    leaves), each lane takes the M-point DFT, and the radix-2
+//    decimation-in-time combination Y[k] = U0[k] + w^k U1[k],
+//    Y[k + M] = U0[k] - w^k U1[k] needs one swap of the lanes' values
+//    (DPP quad permutation 1,0,3,2).
+// Both lanes run the same instructions; lane-dependent signs and twiddles are
+// selected per lane.
+
+__device__ __forceinline__ float swap_pair(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double swap_pair(double v) {
+  int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// lane 1 multiplies by exp(SIGN 2 pi i J / N), lane 0 keeps v
+template <class T, long J, long N, int SIGN>
+__device__ __forceinline__ cplx<T> twiddle_odd(cplx<T> v, int p) {
+  if constexpr (((J % N) + N) % N == 0) {
+    return v;
+  } else {
+    cplx<T> t = twiddle<T, J, N, SIGN>(v);
+    return p ? t : v;
+  }
+}
+
+template <class T, int N, int WI, int SIGN, class LD>
+__device__ __forceinline__ void pair_inverse(cplx<T> (&h)[N / 2], int p, LD&& ld) {
+  constexpr int M = N / 2;
+  const T sg = p ? T(-1) : T(1);
+  sfor<M>([&](auto mm) {
+    constexpr int m = decltype(mm)::value;
+    if constexpr (m < WI) {
+      cplx<T> a = ld(m);
+      if constexpr (m + M < WI) {
+        cplx<T> b = ld(m + M);
+        a.x += sg * b.x;
+        a.y += sg * b.y;
+      }
+      h[m] = twiddle_odd<T, m, N, SIGN>(a, p);
+    } else {
+      h[m] = {T(0), T(0)};
+    }
+  });
+  fft<T, M, SIGN>(h);
+}
+
+// on return u[k] (k < min(M, WO)) is Y[k] on lane 0 and Y[k + M] on lane 1
+template <class T, int N, int WO, int SIGN>
+__device__ __forceinline__ void pair_forward(cplx<T> (&u)[N / 2], int r) {
+  constexpr int M = N / 2;
+  constexpr int K = WO < M ? WO : M;
+  fft<T, M, SIGN>(u);
+  const T sg = r ? T(-1) : T(1);
+  sfor<K>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    cplx<T> own = twiddle_odd<T, k, N, SIGN>(u[k], r);
+    cplx<T> oth = {swap_pair(own.x), swap_pair(own.y)};
+    u[k] = {oth.x + sg * own.x, oth.y + sg * own.y};
+  });
+}
+
 }  // namespace mkpw

@@ -17,14 +17,15 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmkpw.so")
+# MKPW_LIB selects another build of the same library (e.g. an instrumented one)
+LIB_PATH = os.environ.get("MKPW_LIB") or os.path.join(_HERE, "libmkpw.so")
 
 PW_OK, PW_EINVAL, PW_ENOMEM, PW_EDEVICE, PW_ENOCONV, PW_ESTATE = 0, -1, -2, -3, -4, -5
 PW_FP64, PW_MIXED = 0, 1
 STATUS_NAMES = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EDEVICE", -4: "PW_ENOCONV",
                 -5: "PW_ESTATE"}
 
-EXPORTS = ["pw_create", "pw_destroy", "pw_last_error", "pw_set_option", "pw_set_lattice", "pw_set_cutoff",
+EXPORTS = ["pw_create", "pw_destroy", "pw_last_error", "pw_set_option", "pw_get_option", "pw_set_lattice", "pw_set_cutoff",
            "pw_set_kpoints", "pw_get_miller", "pw_set_vloc", "pw_set_projectors", "pw_init_guess", "pw_h_psi",
            "pw_davidson", "pw_dfpt_cg"]
 
@@ -49,6 +50,7 @@ _sig = {
     "pw_destroy": (None, [_vp]),
     "pw_last_error": (C.c_char_p, [_vp]),
     "pw_set_option": (_i, [_vp, C.c_char_p, _i64]),
+    "pw_get_option": (_i, [_vp, C.c_char_p, C.POINTER(_i64)]),
     "pw_set_lattice": (_i, [_vp, _pd]),
     "pw_set_cutoff": (_i, [_vp, _d, _pi]),
     "pw_set_kpoints": (_i, [_vp, _i, _pd, _pi, _pi]),
@@ -120,6 +122,12 @@ def pw_last_error(ctx) -> str:
 
 def pw_set_option(ctx, key: str, value: int):
     return _check(ctx, _lib.pw_set_option(ctx, key.encode(), int(value)))
+
+
+def pw_get_option(ctx, key: str) -> int:
+    v = C.c_int64(0)
+    _check(ctx, _lib.pw_get_option(ctx, key.encode(), C.byref(v)))
+    return int(v.value)
 
 
 def pw_set_lattice(ctx, a):

@@ -59,23 +59,31 @@ def _compare(h, ref, sysm, tol):
     return worst / scale
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("prec,tol", [(0, TOL64), (1, TOL32)])
-def test_hpsi_c1_all_k(prec, tol):
+def test_hpsi_c1_all_k(prec, tol, variant):
+    # odd mesh (15^3): the autotuned and the one-line-per-work-item kernels
+    from paper_2412_01695_amd import mkpw
     cfg = synth.make_config(1)
     torch, s = _system(cfg)
+    mkpw.pw_set_option(s.ctx, "hpsi_variant", variant)
     psi = s.psi_guess()
     h = _run(torch, s, psi, prec)
     ref = _oracle_rows(cfg, s, ham.vtilde(s.vloc), psi, range(cfg.nk))
     print("C1 rel err", _compare(h, ref, s, tol))
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("cid", [2, 3, 4])
-def test_hpsi_k_subset_all_bands(cid):
-    # several tiles of the batch with ragged npw: every 8th..64th k of the full list
+def test_hpsi_k_subset_all_bands(cid, variant):
+    # several tiles of the batch with ragged npw: every 8th..64th k of the full list,
+    # with the autotuned shape and each kernel variant forced
+    from paper_2412_01695_amd import mkpw
     cfg0 = synth.make_config(cid)
     ks = np.arange(0, cfg0.nk, max(1, cfg0.nk // 24))
     cfg = synth.subset(cfg0, ks)
     torch, s = _system(cfg)
+    mkpw.pw_set_option(s.ctx, "hpsi_variant", variant)
     psi = s.psi_guess()
     vt = ham.vtilde(s.vloc)
     for prec, tol in ((0, TOL64), (1, TOL32)):
@@ -84,10 +92,13 @@ def test_hpsi_k_subset_all_bands(cid):
         print(cid, prec, "rel err", _compare(h, ref, s, tol))
 
 
-def test_hpsi_c2_full_batch_sampled():
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_hpsi_c2_full_batch_sampled(variant):
     # the benchmarked launch (512 k x 20 bands), checked on sampled k-points
+    from paper_2412_01695_amd import mkpw
     cfg = synth.make_config(2)
     torch, s = _system(cfg)
+    mkpw.pw_set_option(s.ctx, "hpsi_variant", variant)
     psi = s.psi_guess()
     h = _run(torch, s, psi, 0)
     ks = list(range(0, cfg.nk, 37)) + [cfg.nk - 1]
@@ -167,6 +178,22 @@ def test_repeatable_bitwise():
     a = _run(torch, s, psi, 0)
     b = _run(torch, s, psi, 0)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+def test_slab_widths_agree(variant):
+    # every slab width of the lane-pair kernels gives the same result to rounding
+    from paper_2412_01695_amd import mkpw
+    cfg = synth.subset(synth.make_config(2), np.arange(0, 512, 17))
+    torch, s = _system(cfg)
+    psi = s.psi_guess()
+    mkpw.pw_set_option(s.ctx, "hpsi_variant", variant)
+    outs = []
+    for slab in (1, 3, 7, 24):
+        mkpw.pw_set_option(s.ctx, "hpsi_slab", slab)
+        outs.append(_run(torch, s, psi, 0))
+    for o in outs[1:]:
+        assert np.max(np.abs(o - outs[0])) < 1e-14 * np.max(np.abs(outs[0]))
 
 
 def test_device_initial_guess_matches_generator():
