@@ -189,13 +189,16 @@ def main():
     nkb = cfg.nk * nbnd
     flops_kb, io_kb = algorithmic_work(cfg, sysm.miller, nbnd)
 
-    out = {}
+    def shape():
+        return {k: mkpw.pw_get_option(sysm.ctx, f"hpsi_{k}_tuned") for k in ("variant", "slab", "threads")}
+
+    out, shapes = {}, {}
     if args.only in ("fp64", "both"):
         ms64, wall64 = time_hpsi(torch, mkpw, sysm.ctx, mkpw.PW_FP64, nbnd, psi64, h64, args.steps, args.warmup)
-        out["fp64"] = ms64
+        out["fp64"], shapes["fp64"] = ms64, shape()
     if args.only in ("mixed", "both"):
         ms32, wall32 = time_hpsi(torch, mkpw, sysm.ctx, mkpw.PW_MIXED, nbnd, psi32, h32, args.steps, args.warmup)
-        out["mixed"] = ms32
+        out["mixed"], shapes["mixed"] = ms32, shape()
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -206,8 +209,6 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    shapes = {"variant": mkpw.pw_get_option(sysm.ctx, "hpsi_variant_tuned"),
-              "slab": mkpw.pw_get_option(sysm.ctx, "hpsi_slab_tuned")}
     key = "fp64" if "fp64" in out else "mixed"
     ms = out[key]
     value = nkb / (ms * 1e-3)
@@ -236,13 +237,13 @@ def main():
                      "unit": "TFLOP/s",
                      "frac": achieved_tf / (PEAK_FP64_TFLOPS if key == "fp64" else PEAK_FP32_TFLOPS),
                      "traffic": None,
-                     "kernel": "hpsi_kernel" if shapes["variant"] != 2 else "hpsi_pair_kernel",
-                     "tuned_shape_last": shapes, "flops_per_kband": flops_kb,
+                     "kernel": "hpsi_kernel", "shape": shapes[key], "flops_per_kband": flops_kb,
                      "io_bytes_per_kband": io_kb,
                      "hbm_io_GBs": io_kb * nkb / (ms * 1e-3) / 1e9},
     }
     if "mixed" in out and "fp64" in out:
         res["mixed"] = {"value": nkb / (out["mixed"] * 1e-3), "ms_per_step": out["mixed"], "dtype": "c64",
+                        "shape": shapes["mixed"],
                         "speedup_vs_fp64": out["fp64"] / out["mixed"],
                         "roofline_frac": flops_launch / (out["mixed"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
     eigs = {}

@@ -70,13 +70,16 @@ const char* pw_last_error(const pw_ctx* ctx);
  * (maximum Davidson basis in units of nbnd, default 4, Sec. 5.3), "trace"
  * (nonzero: synchronise and check after every launch), "hpsi_variant"
  * (0 = autotuned on first use, 1 = one work-item per FFT line, 2 = two lanes
- * per line, 3 = two lanes per z and y line and one per x line; 2 and 3 need
- * even meshes) and "hpsi_slab" (0 = autotuned, else the number of z planes
- * transformed together). */
+ * per line, even meshes only), "hpsi_slab" (0 = autotuned, else the number of z planes
+ * transformed together) and "hpsi_threads" (0 = autotuned, else 256, 512 or
+ * 1024 work-items per workgroup where the kernel fits in the registers
+ * that leaves; PW_EINVAL otherwise).  Any nonzero shape option
+ * fixes the shape: the others default to variant 1, 256 work-items and the
+ * widest slab that fits. */
 pw_status pw_set_option(pw_ctx* ctx, const char* key, int64_t value);
 
-/* Read an option (the keys above), or "hpsi_variant_tuned" / "hpsi_slab_tuned"
- * (the shape the autotuner chose on this context's last tuning, 0 if none),
+/* Read an option (the keys above), or "hpsi_variant_tuned" / "hpsi_slab_tuned" /
+ * "hpsi_threads_tuned" (the shape of this context's last H|psi> launch, 0 if none),
  * or "device_bytes" (device memory the context holds now). */
 pw_status pw_get_option(const pw_ctx* ctx, const char* key, int64_t* value);
 

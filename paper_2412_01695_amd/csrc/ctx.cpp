@@ -232,11 +232,15 @@ pw_status pw_set_option(pw_ctx* c, const char* key, int64_t value) {
   } else if (k == "trace") {
     c->trace = value;
   } else if (k == "hpsi_variant") {
-    if (value < 0 || value > 3) return set_err(c, PW_EINVAL, "hpsi_variant must be 0, 1, 2 or 3");
+    if (value < 0 || value > 2) return set_err(c, PW_EINVAL, "hpsi_variant must be 0, 1 or 2");
     c->hpsi_variant = value;
   } else if (k == "hpsi_slab") {
     if (value < 0 || value > 512) return set_err(c, PW_EINVAL, "hpsi_slab must be in [0, 512]");
     c->hpsi_slab = value;
+  } else if (k == "hpsi_threads") {
+    if (value != 0 && value != 256 && value != 512 && value != 1024)
+      return set_err(c, PW_EINVAL, "hpsi_threads must be 0, 256, 512 or 1024");
+    c->hpsi_threads = value;
   } else {
     return set_err(c, PW_EINVAL, "unknown option '" + k + "'");
   }
@@ -252,7 +256,9 @@ pw_status pw_get_option(const pw_ctx* c, const char* key, int64_t* value) {
   else if (k == "hpsi_variant") *value = c->hpsi_variant;
   else if (k == "hpsi_slab") *value = c->hpsi_slab;
   else if (k == "hpsi_variant_tuned") *value = c->last_hpsi_variant;
+  else if (k == "hpsi_threads") *value = c->hpsi_threads;
   else if (k == "hpsi_slab_tuned") *value = c->last_hpsi_slab;
+  else if (k == "hpsi_threads_tuned") *value = c->last_hpsi_threads;
   else if (k == "device_bytes") {
     int64_t b = 0;
     for (auto& m : c->owned) b += (int64_t)m.bytes;

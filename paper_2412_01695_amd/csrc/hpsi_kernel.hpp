@@ -1,0 +1,738 @@
+// Batched H|psi> over many k-points: the fused kernel and its launch machinery,
+// instantiated per mesh size in hpsi_n<N>.hip.
+//
+// One workgroup applies H to one (k, band) row (Sec. 3, H application, all
+// k-points and bands of the batch in one launch, Algorithm new_gpu):
+//   1. scatter psi(G) into LDS "sticks" (one row per (m1', m2') that holds
+//      plane waves);
+//   2. inverse 1D transforms along z on the sticks (Eq. zfft) -- and, on the
+//      waves the sticks leave idle, the projector overlaps
+//      lambda_q = sum_G beta_q(k+G)^* psi(G) (Eq. lambdah) and
+//      gamma = D lambda (Eq. gamma);
+//   3. for a slab of z planes at a time: inverse along y (Eq. yfft) on the
+//      occupied x columns, then along x (Eq. xfft) for every (y, z) line,
+//      multiply by V(r)/N_r, forward along x, forward along y (Eq. fwFFT);
+//   4. forward along z on the sticks;
+//   5. gather back to the sphere and add the kinetic term (1/2)|k+G|^2 psi
+//      and the nonlocal term sum_q gamma_q beta_q(k+G) (Eq. finalnl).
+// Each 1D line is transformed in registers (fft.hpp), by one work-item or by
+// a pair of adjacent lanes; LDS carries the transposes between axes.  Nothing
+// but psi, beta, the per-k maps and V(r) is read from memory and nothing but
+// H psi is written: the paper's N_k x N_b full FFT meshes in global memory are
+// never formed.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fft.hpp"
+#include "internal.hpp"
+
+namespace mkpw {
+constexpr int kProjChunk = 8;
+constexpr int kMaxProj = 32;
+
+// lane i takes lane i^1 (DPP quad permutation 1,0,3,2), i^2 (2,3,0,1), and the
+// mirrors within 8 and 16 lanes
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 64 lanes of a wavefront, returned on every lane: four DPP steps
+// give each 16-lane row its sum, two lane shuffles combine the rows
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v += dpp<0xB1>(v);   // quad_perm 1,0,3,2
+  v += dpp<0x4E>(v);   // quad_perm 2,3,0,1
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// The lane's half as a value the compiler cannot see through, so that the
+// per-lane sign and twiddle selects stay next to their use instead of being
+// hoisted out of the loops into long-lived registers.
+__device__ __forceinline__ int lane_half(int h) {
+  asm volatile("" : "+v"(h));
+  return h;
+}
+
+// Per-row context.
+template <class T>
+struct Row {
+  int ik, npw, ns, npwx;
+  const cplx<T>* p;
+  cplx<T>* hp;
+  const int* gmap;
+  const short* sof;
+  const double* kin;
+  const cplx<T>* bk;
+};
+
+// Decode the block into a (k, vector) row; false when the block has no row.
+template <class T>
+__device__ __forceinline__ bool row_of_block(const KTables& t, const VecSel& sel, int nproj, const cplx<T>* beta,
+                                             const cplx<T>* psi, cplx<T>* hpsi, int per_xcd, int ntask, Row<T>& r) {
+  // XCD-aware order: consecutive (k, band) tasks run on the same XCD (blocks
+  // are dealt to the 8 XCDs round-robin), so a k-point's projectors and maps
+  // are fetched into one L2.
+  const int bid = blockIdx.x;
+  const int task = (bid & 7) * per_xcd + (bid >> 3);
+  if (task >= ntask) return false;
+  const int ik = task / sel.nvec;
+  const int iv = task - ik * sel.nvec;
+  const int cnt = sel.cnt ? sel.cnt[ik] : sel.nvec;
+  if (iv >= cnt) return false;
+  const int off = sel.off ? sel.off[ik] : 0;
+  r.ik = ik;
+  r.npwx = t.npwx;
+  const long row = (long)ik * sel.kstride + (long)(off + iv) * t.npwx;
+  r.p = psi + row;
+  r.hp = hpsi + row;
+  r.npw = t.npw[ik];
+  r.ns = t.nstick[ik];
+  r.gmap = t.gmap + (long)ik * t.npwx;
+  r.sof = t.sof + (long)ik * t.wx * t.wy;
+  r.kin = t.kin + (long)ik * t.npwx;
+  r.bk = beta + (long)ik * nproj * t.npwx;
+  return true;
+}
+
+// gamma_p = sum_q D_pq lambda_q (Eq. gamma), lambda_q summed over the nslot
+// per-wave partial sums in red[w][q]; D is staged in LDS (dl[p][q]).
+template <class T>
+__device__ __forceinline__ void finish_gamma(int p, int nproj, const cplx<T>* dl, const cplx<T>* red, int nslot,
+                                             cplx<T>* gam) {
+  cplx<T> g = {T(0), T(0)};
+  for (int q = 0; q < nproj; ++q) {
+    cplx<T> lam = {T(0), T(0)};
+    for (int w = 0; w < nslot; ++w) lam = cadd(lam, red[w * nproj + q]);
+    g = cadd(g, cmul(dl[p * nproj + q], lam));
+  }
+  gam[p] = g;
+}
+
+// Gather the local term from the sticks and add (1/2)|k+G|^2 psi and
+// sum_q gamma_q beta_q (Eq. finalnl); the padding of the row is written as zero.
+template <class T, int ZS, int NT>
+__device__ __forceinline__ void gather_add(const Row<T>& r, int nproj, const cplx<T>* Z, const cplx<T>* gam) {
+  const cplx<T> zero = {T(0), T(0)};
+  for (int g = threadIdx.x; g < r.npwx; g += NT) {
+    cplx<T> h = zero;
+    if (g < r.npw) {
+      int gm = r.gmap[g];
+      h = Z[(gm >> 8) * ZS + (gm & 255)];
+      cplx<T> v = r.p[g];
+      T kk = (T)r.kin[g];
+      h.x += kk * v.x;
+      h.y += kk * v.y;
+      for (int q = 0; q < nproj; ++q) h = cadd(h, cmul(r.bk[(long)q * r.npwx + g], gam[q]));
+    }
+    r.hp[g] = h;
+  }
+}
+
+// ---------------------------------------------------------------- 1D passes
+// Each pass comes in a one-work-item-per-line form and, for even N, a
+// lane-pair form (pair_inverse / pair_forward in fft.hpp).
+
+// inverse along one line: WC inputs from ld(m) -> N outputs to st(l, value)
+template <class T, int N, int WC, bool PAIR, class LD, class ST>
+__device__ __forceinline__ void line_inverse(int h, LD&& ld, ST&& st) {
+  if constexpr (PAIR) {
+    constexpr int M = N / 2;
+    cplx<T> v[M];
+    pair_inverse<T, N, WC, +1>(v, h, ld);
+    sfor<M>([&](auto j) { st(2 * decltype(j)::value + h, v[decltype(j)::value]); });
+  } else {
+    cplx<T> v[N];
+    sfor<N>([&](auto j) {
+      constexpr int J = decltype(j)::value;
+      if constexpr (J < WC) v[J] = ld(J);
+      else v[J] = {T(0), T(0)};
+    });
+    fft<T, N, +1>(v);
+    sfor<N>([&](auto j) { st(decltype(j)::value, v[decltype(j)::value]); });
+  }
+}
+
+// forward along one line: N inputs from ld(l) -> the first WC outputs to st(m, value)
+template <class T, int N, int WC, bool PAIR, class LD, class ST>
+__device__ __forceinline__ void line_forward(int h, LD&& ld, ST&& st) {
+  if constexpr (PAIR) {
+    constexpr int M = N / 2;
+    constexpr int KO = WC < M ? WC : M;
+    cplx<T> v[M];
+    sfor<M>([&](auto j) { v[decltype(j)::value] = ld(2 * decltype(j)::value + h); });
+    pair_forward<T, N, WC, -1>(v, h);
+    sfor<KO>([&](auto k) { st(decltype(k)::value + h * M, v[decltype(k)::value]); });
+  } else {
+    cplx<T> v[N];
+    sfor<N>([&](auto j) { v[decltype(j)::value] = ld(decltype(j)::value); });
+    fft<T, N, -1>(v);
+    sfor<WC>([&](auto j) { st(decltype(j)::value, v[decltype(j)::value]); });
+  }
+}
+
+// x line: WC inputs -> N points -> * V/N_r -> forward -> WC outputs.  vat(J)
+// gives V at the J-th point the work-item holds: point J, or 2 J + h of a pair.
+template <class T, int N, int WC, bool PAIR, class LD, class VAT, class ST>
+__device__ __forceinline__ void line_xv(int h, LD&& ld, VAT&& vat, ST&& st) {
+  if constexpr (PAIR) {
+    constexpr int M = N / 2;
+    constexpr int KO = WC < M ? WC : M;
+    cplx<T> v[M];
+    pair_inverse<T, N, WC, +1>(v, h, ld);
+    sfor<M>([&](auto j) {
+      constexpr int J = decltype(j)::value;
+      T f = vat(J);  // point 2 J + h of the line
+      v[J].x *= f;
+      v[J].y *= f;
+    });
+    pair_forward<T, N, WC, -1>(v, h);
+    sfor<KO>([&](auto k) { st(decltype(k)::value + h * M, v[decltype(k)::value]); });
+  } else {
+    cplx<T> v[N];
+    sfor<N>([&](auto j) {
+      constexpr int J = decltype(j)::value;
+      if constexpr (J < WC) v[J] = ld(J);
+      else v[J] = {T(0), T(0)};
+    });
+    fft<T, N, +1>(v);
+    sfor<N>([&](auto l) {
+      constexpr int L = decltype(l)::value;
+      T f = vat(L);
+      v[L].x *= f;
+      v[L].y *= f;
+    });
+    fft<T, N, -1>(v);
+    sfor<WC>([&](auto j) { st(decltype(j)::value, v[decltype(j)::value]); });
+  }
+}
+
+// ---------------------------------------------------------------- the kernel
+// LDS layout of one workgroup, in elements of cplx<T> unless noted.
+struct HpsiLds {
+  size_t z, y, red, gam, dl, sof_bytes, bytes;
+};
+template <class T, int N, int WC>
+__host__ __device__ inline HpsiLds hpsi_lds_layout(int smax, int wx, int l3c, int nproj, int threads) {
+  const size_t cs = sizeof(cplx<T>);
+  const int np = nproj > 0 ? nproj : 1;
+  HpsiLds L;
+  L.z = (size_t)(smax + 2) * (N | 1);  // sticks, then one zero row and one write-sink row
+  L.y = (size_t)l3c * N * (wx | 1);    // slab planes
+  L.red = (size_t)(threads / 64) * np; // per-wave projector partial sums
+  L.gam = np;
+  L.dl = (size_t)np * np;
+  L.sof_bytes = ((size_t)wx * WC * sizeof(short) + 15) / 16 * 16;
+  L.bytes = (L.z + L.y + L.red + L.gam + L.dl) * cs + L.sof_bytes;
+  return L;
+}
+
+// ZYP: z and y passes in lane pairs; XP: x pass in lane pairs (even N only).
+// WC: compile-time capacity of the Miller window along each axis (>= the
+// actual extents wx, wy, wz); entries beyond the actual window are zero.
+// NT: work-items per workgroup (256, 512 or 1024).
+template <class T, int N, int WC, bool ZYP, bool XP, int NT>
+__global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int nproj,
+                                                  const cplx<T>* __restrict__ beta,
+                                                  const cplx<T>* __restrict__ dij,
+                                                  const T* __restrict__ vr,
+                                                  const cplx<T>* __restrict__ psi,
+                                                  cplx<T>* __restrict__ hpsi, int l3c, int ys,
+                                                  int per_xcd, int ntask) {
+  static_assert(!(ZYP || XP) || N % 2 == 0, "lane-pair passes need an even length");
+  Row<T> r;
+  if (!row_of_block(t, sel, nproj, beta, psi, hpsi, per_xcd, ntask, r)) return;
+  const int wx = t.wx, wy = t.wy;
+  const int ns = r.ns;
+  constexpr int ZS = N | 1;  // stick row stride (odd: no LDS bank aliasing between sticks)
+  constexpr int NW = NT / 64;
+  const int zrow = t.smax, sink = t.smax + 1;  // all-zero stick, write-only stick
+
+  const HpsiLds L = hpsi_lds_layout<T, N, WC>(t.smax, wx, l3c, nproj, NT);
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* Z = reinterpret_cast<cplx<T>*>(smem);  // [smax + 2][ZS]
+  cplx<T>* Y = Z + L.z;                           // [l3c][N][ys], ys odd >= wx
+  cplx<T>* red = Y + L.y;                         // [NW][nproj]
+  cplx<T>* gam = red + L.red;                     // [nproj]
+  cplx<T>* dl = gam + L.gam;                      // [nproj][nproj]
+  short* sof = reinterpret_cast<short*>(dl + L.dl);  // [wx][WC] stick of (m1', m2'), zrow if none
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int h0 = tid & 1;
+  const cplx<T> zero = {T(0), T(0)};
+  constexpr int kZyStride = ZYP ? NT / 2 : NT;
+  constexpr int kXStride = XP ? NT / 2 : NT;
+  const int zy_slot = ZYP ? tid >> 1 : tid;
+  const int x_slot = XP ? tid >> 1 : tid;
+
+  // ---- 0. start the loads of the first plane waves of this work-item (psi,
+  //         map, first projectors) so that they arrive during the zeroing
+  constexpr int kPre = 2;
+  const int npre = min(nproj, kProjChunk);
+  cplx<T> pv[kPre], bv[kPre][kProjChunk];
+  int gv[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    const int g = tid + u * NT;
+    if (g < r.npw) {
+      pv[u] = r.p[g];
+      gv[u] = r.gmap[g];
+#pragma unroll
+      for (int q = 0; q < kProjChunk; ++q)
+        if (q < npre) bv[u][q] = r.bk[(long)q * r.npwx + g];
+    }
+  }
+
+  // ---- 1. zero the stick windows and the zero row, stage the stick map and D
+  for (int i = tid; i < ns * WC; i += NT) {
+    int s = i / WC, j = i - s * WC;
+    Z[s * ZS + j] = zero;
+  }
+  for (int i = tid; i < N; i += NT) Z[zrow * ZS + i] = zero;
+  for (int i = tid; i < wx * WC; i += NT) {
+    const int m1 = i / WC, m2 = i - m1 * WC;
+    int s = m2 < wy ? r.sof[m1 * wy + m2] : -1;
+    sof[i] = (short)(s >= 0 ? s : zrow);
+  }
+  for (int i = tid; i < nproj * nproj; i += NT) dl[i] = dij[i];
+  __syncthreads();
+
+  // ---- 2. scatter psi into the sticks; the same loads give the partial
+  //         projector overlaps lambda_q = sum_G beta_q^* psi (Eq. lambdah),
+  //         summed over each wave into red[wave][q]
+  {
+    T ax[kProjChunk], ay[kProjChunk];
+    auto acc = [&](int q, cplx<T> b, cplx<T> v) {
+      ax[q] += b.x * v.x + b.y * v.y;  // conj(b) * v
+      ay[q] += b.x * v.y - b.y * v.x;
+    };
+    auto flush = [&](int q0) {
+#pragma unroll
+      for (int q = 0; q < kProjChunk; ++q) {
+        if (q0 + q < nproj) {
+          const T sx = wave_sum(ax[q]), sy = wave_sum(ay[q]);
+          if (lane == 0) red[wave * nproj + q0 + q] = {sx, sy};
+        }
+      }
+    };
+#pragma unroll
+    for (int q = 0; q < kProjChunk; ++q) ax[q] = ay[q] = T(0);
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      if (tid + u * NT < r.npw) {
+        Z[(gv[u] >> 8) * ZS + (gv[u] & 255)] = pv[u];
+#pragma unroll
+        for (int q = 0; q < kProjChunk; ++q)
+          if (q < npre) acc(q, bv[u][q], pv[u]);
+      }
+    }
+    for (int g = tid + kPre * NT; g < r.npw; g += NT) {
+      const cplx<T> v = r.p[g];
+      const int gm = r.gmap[g];
+      Z[(gm >> 8) * ZS + (gm & 255)] = v;
+#pragma unroll
+      for (int q = 0; q < kProjChunk; ++q)
+        if (q < npre) acc(q, r.bk[(long)q * r.npwx + g], v);
+    }
+    flush(0);
+    for (int q0 = kProjChunk; q0 < nproj; q0 += kProjChunk) {  // more than kProjChunk projectors
+#pragma unroll
+      for (int q = 0; q < kProjChunk; ++q) ax[q] = ay[q] = T(0);
+      for (int g = tid; g < r.npw; g += NT) {
+        const cplx<T> v = r.p[g];
+#pragma unroll
+        for (int q = 0; q < kProjChunk; ++q)
+          if (q0 + q < nproj) acc(q, r.bk[(long)(q0 + q) * r.npwx + g], v);
+      }
+      flush(q0);
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. inverse z on the sticks (W -> N), on as few waves as hold them;
+  //         gamma = D lambda on the last wave
+  {
+    const int zlanes = (ZYP ? 2 : 1) * ns;
+    const int zwaves = min(NW, (zlanes + 63) / 64);
+    if (wave < zwaves) {
+      for (int s = zy_slot; s < ns; s += (ZYP ? zwaves * 32 : zwaves * 64)) {
+        const int h = lane_half(h0);
+        cplx<T>* zr = Z + s * ZS;
+        line_inverse<T, N, WC, ZYP>(h, [&](int m) { return zr[m]; }, [&](int l, cplx<T> v) { zr[l] = v; });
+      }
+    }
+    // read by the gather; the barriers of the slab loop publish it
+    if (wave == NW - 1 && lane < nproj) finish_gamma(lane, nproj, dl, red, NW, gam);
+  }
+  __syncthreads();
+
+  // ---- 4. slabs of z planes.  V is stored permuted per slab so that the
+  //         x-line work-items of a slab read it contiguously: Vp[slab][l1][lc][l2].
+  for (int l30 = 0; l30 < N; l30 += l3c) {
+    const int nl = min(l3c, N - l30);
+    const T* vslab = vr + (size_t)l30 * N * N;
+    // inverse y on the occupied columns m1' < wx: W inputs (from the sticks) -> N outputs
+    for (int i = zy_slot; i < wx * nl; i += kZyStride) {
+      const int h = lane_half(h0);
+      const int lc = i / wx, m1 = i - lc * wx, l3 = l30 + lc;
+      cplx<T>* y = Y + (size_t)lc * N * ys + m1;
+      const short* so = sof + m1 * WC;
+      line_inverse<T, N, WC, ZYP>(
+          h, [&](int m) { return Z[so[m] * ZS + l3]; }, [&](int l, cplx<T> v) { y[l * ys] = v; });
+    }
+    __syncthreads();
+    // x lines: W inputs -> N points -> * V/N_r -> forward -> W outputs
+    for (int i = x_slot; i < N * nl; i += kXStride) {
+      const int h = lane_half(h0);
+      cplx<T>* y = Y + (size_t)i * ys;  // i = lc * N + l2
+      const T* vv = vslab + i;
+      line_xv<T, N, WC, XP>(
+          h, [&](int m) { return m < wx ? y[m] : zero; },
+          [&](int j) { return vv[(size_t)(XP ? 2 * j + h : j) * nl * N]; },
+          [&](int m, cplx<T> v) {
+            if (m < wx) y[m] = v;
+          });
+    }
+    __syncthreads();
+    // forward y: N inputs -> W outputs, back into the sticks (outputs with no
+    // stick go to the write-only row)
+    for (int i = zy_slot; i < wx * nl; i += kZyStride) {
+      const int h = lane_half(h0);
+      const int lc = i / wx, m1 = i - lc * wx, l3 = l30 + lc;
+      const cplx<T>* y = Y + (size_t)lc * N * ys + m1;
+      const short* so = sof + m1 * WC;
+      line_forward<T, N, WC, ZYP>(
+          h, [&](int l) { return y[l * ys]; },
+          [&](int m2, cplx<T> v) {
+            if (m2 < WC) {  // the second lane of a pair also returns outputs M.. of the line
+              const int s = so[m2];
+              Z[(s == zrow ? sink : s) * ZS + l3] = v;
+            }
+          });
+    }
+    __syncthreads();
+  }
+
+  // ---- 5. forward z on the sticks: N inputs -> W outputs (in place)
+  for (int s = zy_slot; s < ns; s += kZyStride) {
+    const int h = lane_half(h0);
+    cplx<T>* zr = Z + s * ZS;
+    line_forward<T, N, WC, ZYP>(
+        h, [&](int l) { return zr[l]; },
+        [&](int m3, cplx<T> v) {
+          if (m3 < WC) zr[m3] = v;
+        });
+  }
+  __syncthreads();
+
+  // ---- 6. gather + kinetic + nonlocal
+  gather_add<T, ZS, NT>(r, nproj, Z, gam);
+}
+
+// ---------------------------------------------------------------- launching
+
+// V/N_r permuted for a slab width: Vp[l30 .. l30+nl)[l1][lc][l2] = V[l1][l2][l30+lc]
+template <class T>
+__global__ void permute_v_kernel(const T* __restrict__ v, T* __restrict__ vp, int n, int l3c) {
+  const long nr = (long)n * n * n;
+  for (long o = blockIdx.x * (long)blockDim.x + threadIdx.x; o < nr; o += (long)gridDim.x * blockDim.x) {
+    const long slab_len = (long)l3c * n * n;
+    const int l30 = (int)(o / slab_len) * l3c;
+    const int nl = min(l3c, n - l30);
+    long rr = o - (long)l30 * n * n;
+    const int l1 = (int)(rr / ((long)nl * n));
+    rr -= (long)l1 * nl * n;
+    const int lc = (int)(rr / n), l2 = (int)(rr % n);
+    vp[o] = v[((long)l1 * n + l2) * n + l30 + lc];
+  }
+}
+
+// Shape of one launch: kernel variant (1 = one work-item per line, 2 = lane
+// pair per line, even N only), slab width in z planes, work-items per workgroup.
+struct HpsiShape {
+  int variant = 1;
+  int l3c = 1;
+  int threads = 256;
+};
+
+// Autotuning results shared by every context of the process (hpsi.hip).
+extern std::mutex g_hpsi_tune_mu;
+extern std::map<std::vector<long>, HpsiShape> g_hpsi_tuned;
+
+constexpr size_t kLdsPerCu = 160 * 1024;
+
+template <class T, int N, int WC>
+size_t hpsi_lds(const KTables& t, int l3c, int nproj, int threads) {
+  return hpsi_lds_layout<T, N, WC>(t.smax, t.wx, l3c, nproj, threads).bytes;
+}
+
+// Workgroup sizes instantiated: 512 work-items leave 256 registers per lane
+// and 1024 leave 128, so each is built only where the kernel fits without
+// spilling (the double precision one-line-per-work-item passes need the full
+// 512 from N = 30 on).
+template <class T, int N, int VARIANT>
+constexpr bool allow_512() {
+  return !(sizeof(T) == 8 && VARIANT != 2 && N >= 30);
+}
+template <class T, int N, int VARIANT>
+constexpr bool allow_1024() {
+  return sizeof(T) == 4 ? (VARIANT == 2 || N <= 20) : (VARIANT == 2 && N <= 24);
+}
+
+template <class T, int N, int WC, int VARIANT>
+const void* kernel_for(int threads) {
+  constexpr bool ZYP = VARIANT != 1, XP = VARIANT == 2;
+  if (threads == 256) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 256>;
+  if constexpr (allow_512<T, N, VARIANT>()) {
+    if (threads == 512) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 512>;
+  }
+  if constexpr (allow_1024<T, N, VARIANT>()) {
+    if (threads == 1024) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 1024>;
+  }
+  return nullptr;
+}
+
+template <class T, int N, int WC>
+const void* hpsi_kernel_ptr(const HpsiShape& sh) {
+  if constexpr (N % 2 == 0) {
+    if (sh.variant == 2) return kernel_for<T, N, WC, 2>(sh.threads);
+  }
+  if (sh.variant == 1) return kernel_for<T, N, WC, 1>(sh.threads);
+  return nullptr;
+}
+
+template <class T, int N, int WC>
+pw_status launch_shape(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st, HpsiShape sh) {
+  KTables t = c->tables();
+  const int ys = t.wx | 1;
+  const int l3c = sh.l3c;
+  const int nproj_k = c->have_proj ? c->nproj : 0;
+  const size_t lds = hpsi_lds<T, N, WC>(t, l3c, nproj_k, sh.threads);
+  const void* kern = hpsi_kernel_ptr<T, N, WC>(sh);
+  if (!kern) return set_err(c, PW_EINVAL, "no H|psi> kernel for this variant and workgroup size");
+  {
+    pw_status s = ensure_lds_limit(c, kern, lds);
+    if (s != PW_OK) return s;
+  }
+  const long ntask = (long)t.nk * sel.nvec;
+  if (ntask <= 0) return PW_OK;
+  if (ntask > (1L << 30)) return set_err(c, PW_EINVAL, "too many (k, band) rows in one call");
+  const bool fp64 = sizeof(T) == 8;
+  // permuted potential for this slab width (rebuilt when the width changes)
+  int& have = fp64 ? c->vperm_l3c64 : c->vperm_l3c32;
+  void*& vp = fp64 ? c->d_vperm64 : c->d_vperm32;
+  if (have != l3c || !vp) {
+    if (!vp) {
+      pw_status s = dev_alloc(c, (size_t)N * N * N * sizeof(T), &vp);
+      if (s != PW_OK) return s;
+    }
+    const T* v = (const T*)(fp64 ? (const void*)c->d_v64 : (const void*)c->d_v32);
+    hipLaunchKernelGGL(permute_v_kernel<T>, dim3(64), dim3(256), 0, st, v, (T*)vp, N, l3c);
+    have = l3c;
+  }
+  int per_xcd = (int)((ntask + 7) / 8);
+  int nproj = c->have_proj ? c->nproj : 0;
+  const cplx<T>* beta = (const cplx<T>*)(fp64 ? c->d_beta64 : c->d_beta32);
+  const cplx<T>* dij = (const cplx<T>*)(fp64 ? c->d_dij64 : c->d_dij32);
+  const T* vpt = (const T*)vp;
+  const cplx<T>* pin = (const cplx<T>*)psi;
+  cplx<T>* pout = (cplx<T>*)hpsi;
+  int l3c_arg = l3c, ys_arg = ys, ntask_arg = (int)ntask;
+  VecSel sel_arg = sel;
+  void* args[] = {&t, &sel_arg, &nproj, &beta, &dij, &vpt, &pin, &pout, &l3c_arg, &ys_arg, &per_xcd, &ntask_arg};
+  hipError_t e = hipLaunchKernel(kern, dim3(8u * (unsigned)per_xcd), dim3(sh.threads), args, lds, st);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return set_err(c, PW_EDEVICE, std::string("h_psi launch: ") + hipGetErrorString(e));
+  c->last_hpsi_variant = sh.variant;
+  c->last_hpsi_slab = sh.l3c;
+  c->last_hpsi_threads = sh.threads;
+  if (c->trace) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return set_err(c, PW_EDEVICE, std::string("h_psi: ") + hipGetErrorString(e));
+  }
+  return PW_OK;
+}
+
+// Workgroups of this kernel one CU can hold by registers (4 SIMDs with 512
+// VGPRs per lane, allocated in blocks of 8); 0 if the kernel spills registers
+// to scratch memory (left out of the autotuning).
+inline int wgs_by_vgpr(const void* kern, int threads) {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, kern) != hipSuccess || a.numRegs <= 0) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  if (a.localSizeBytes > 0) return 0;
+  const int v = (a.numRegs + 7) / 8 * 8;
+  const int waves_per_simd = std::min(8, 512 / v);
+  return std::max(1, waves_per_simd * 4 / (threads / 64));
+}
+
+// Candidate shapes: for each variant and workgroup size, the widest slab that
+// fits in the LDS share for 1, 2 or 3 workgroups per CU (as many as the
+// registers allow), capped where every x line already has its own work-item
+// (or lane pair).
+template <class T, int N, int WC>
+std::vector<HpsiShape> hpsi_candidates(const KTables& t, int nproj) {
+  std::vector<HpsiShape> out;
+  for (int variant : {1, 2}) {
+    if (variant != 1 && N % 2) continue;
+    for (int threads : {256, 512, 1024}) {
+      const void* kern = hpsi_kernel_ptr<T, N, WC>({variant, 1, threads});
+      if (!kern) continue;
+      const int lanes = variant == 2 ? 2 : 1;  // work-items per x line
+      const int cap = std::min(N, std::max(1, threads / (lanes * N)));
+      const int max_wg = std::min(3, wgs_by_vgpr(kern, threads));  // 0: spills, skipped
+      for (int wg = 1; wg <= max_wg; ++wg) {
+        const size_t share = kLdsPerCu / wg;
+        int l3c = wg == 1 ? N : cap;
+        while (l3c > 1 && hpsi_lds<T, N, WC>(t, l3c, nproj, threads) > share) --l3c;
+        if (hpsi_lds<T, N, WC>(t, l3c, nproj, threads) > kLdsPerCu) continue;
+        bool dup = false;
+        for (auto& o : out) dup = dup || (o.variant == variant && o.l3c == l3c && o.threads == threads);
+        if (!dup) out.push_back({variant, l3c, threads});
+      }
+    }
+  }
+  return out;
+}
+
+template <class T, int N, int WC>
+pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st) {
+  KTables t = c->tables();
+  const int nproj = c->have_proj ? c->nproj : 0;
+  if (c->hpsi_variant != 0 || c->hpsi_slab != 0 || c->hpsi_threads != 0) {  // explicit shape
+    if (c->hpsi_variant >= 2 && N % 2) return set_err(c, PW_EINVAL, "lane-pair variants need an even mesh");
+    HpsiShape sh;
+    sh.variant = c->hpsi_variant ? (int)c->hpsi_variant : 1;
+    sh.threads = c->hpsi_threads ? (int)c->hpsi_threads : 256;
+    if (!hpsi_kernel_ptr<T, N, WC>(sh))
+      return set_err(c, PW_EINVAL, "no H|psi> kernel for this variant and workgroup size on this mesh");
+    const int lanes = sh.variant == 2 ? 2 : 1;
+    sh.l3c = c->hpsi_slab ? (int)std::min<int64_t>(c->hpsi_slab, N)
+                          : std::min(N, std::max(1, sh.threads / (lanes * N)));
+    if (!c->hpsi_slab)
+      while (sh.l3c > 1 && hpsi_lds<T, N, WC>(t, sh.l3c, nproj, sh.threads) > kLdsPerCu) --sh.l3c;
+    if (hpsi_lds<T, N, WC>(t, sh.l3c, nproj, sh.threads) > kLdsPerCu)
+      return set_err(c, PW_EINVAL, "requested H|psi> slab does not fit in LDS");
+    return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh);
+  }
+  // autotune once per (precision, mesh, window, stick count, row-count bucket)
+  long rows = 1;
+  while (rows < (long)t.nk * sel.nvec) rows <<= 1;
+  const std::vector<long> key = {(long)sizeof(T), N, WC, t.smax, t.wx, nproj, rows};
+  {
+    std::lock_guard<std::mutex> lk(g_hpsi_tune_mu);
+    auto it = g_hpsi_tuned.find(key);
+    if (it != g_hpsi_tuned.end()) return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, it->second);
+  }
+  auto cands = hpsi_candidates<T, N, WC>(t, nproj);
+  if (cands.empty()) return set_err(c, PW_EINVAL, "H|psi> working set does not fit in LDS for this mesh");
+  HpsiShape sh = cands[0];
+  if (cands.size() > 1) {
+    // two rounds: every candidate once (one warm-up launch, which also builds
+    // its permuted V, then two timed), then the three fastest again with five
+    // timed launches each
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(c, PW_EDEVICE, "hipEventCreate failed");
+    }
+    pw_status s = PW_OK;
+    auto time_it = [&](const HpsiShape& cand, int reps, float* ms) {
+      if ((s = launch_shape<T, N, WC>(c, sel, psi, hpsi, st, cand)) != PW_OK) return false;
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < reps; ++r)
+        if ((s = launch_shape<T, N, WC>(c, sel, psi, hpsi, st, cand)) != PW_OK) return false;
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      (void)hipEventElapsedTime(ms, e0, e1);
+      *ms /= reps;
+      return true;
+    };
+    std::vector<std::pair<float, size_t>> t1;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      float ms = 0.f;
+      if (!time_it(cands[i], 2, &ms)) break;
+      t1.push_back({ms, i});
+    }
+    if (s == PW_OK) {
+      std::sort(t1.begin(), t1.end());
+      float best = 1e30f;
+      for (size_t j = 0; j < std::min<size_t>(3, t1.size()); ++j) {
+        float ms = 0.f;
+        if (!time_it(cands[t1[j].second], 5, &ms)) break;
+        if (ms < best) {
+          best = ms;
+          sh = cands[t1[j].second];
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != PW_OK) return s;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_hpsi_tune_mu);
+    g_hpsi_tuned[key] = sh;
+  }
+  return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh);
+}
+
+// Window capacities built for an N^3 mesh: every other value from about N/3
+// to N/2 + 2 (the usual range of the wave-function window on a density-sized
+// mesh), then N.  A launch takes the smallest one that holds the window, so
+// at most one padded input per line is transformed.
+template <int N>
+constexpr int wc_first() {
+  return (N + 2) / 3 > 5 ? (N + 2) / 3 : 5;
+}
+template <int N, int WC>
+constexpr int wc_next() {
+  return WC >= N / 2 + 2 ? N : (WC + 2 < N / 2 + 2 ? WC + 2 : N / 2 + 2);
+}
+
+template <class T, int N, int WC>
+pw_status launch_ladder(pw_ctx* c, int w, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st) {
+  if constexpr (WC >= N) {
+    return launch_one<T, N, N>(c, sel, psi, hpsi, st);
+  } else {
+    if (w <= WC) return launch_one<T, N, WC>(c, sel, psi, hpsi, st);
+    return launch_ladder<T, N, wc_next<N, WC>()>(c, w, sel, psi, hpsi, st);
+  }
+}
+
+// H|psi> on an N^3 mesh
+template <class T, int N>
+pw_status launch_n(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st) {
+  const int w = std::max(c->wx, std::max(c->wy, c->wz));
+  return launch_ladder<T, N, wc_first<N>()>(c, w, sel, psi, hpsi, st);
+}
+
+// one translation unit per mesh size instantiates both precisions; the
+// dispatcher only declares them
+#define MKPW_HPSI_INSTANTIATE(N)                                                                    \
+  template pw_status launch_n<double, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t); \
+  template pw_status launch_n<float, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t);
+#define MKPW_HPSI_EXTERN(N)                                                                                \
+  extern template pw_status launch_n<double, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t); \
+  extern template pw_status launch_n<float, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t);
+
+}  // namespace mkpw

@@ -1,0 +1,6 @@
+// H|psi> kernels and launcher for the 15^3 FFT mesh, both precisions.
+#include "hpsi_kernel.hpp"
+
+namespace mkpw {
+MKPW_HPSI_INSTANTIATE(15)
+}  // namespace mkpw

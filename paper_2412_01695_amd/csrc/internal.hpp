@@ -106,9 +106,10 @@ struct pw_ctx {
   int64_t hbm_budget = 0;  // 0 = no budget
   int64_t trace = 0;
   int64_t dav_basis_factor = 4;
-  int64_t hpsi_variant = 0;  // 0 = autotuned, 1 = one work-item per line, 2 = lane pair per line
+  int64_t hpsi_variant = 0;  // 0 = autotuned, else the kernel variant (1, 2)
   int64_t hpsi_slab = 0;     // 0 = autotuned, else z planes per slab
-  int last_hpsi_variant = 0, last_hpsi_slab = 0;  // shape chosen by the last autotuning
+  int64_t hpsi_threads = 0;  // 0 = autotuned, else work-items per workgroup
+  int last_hpsi_variant = 0, last_hpsi_slab = 0, last_hpsi_threads = 0;  // shape of the last H|psi> launch
 
   // crystal and basis
   bool have_lattice = false, have_cutoff = false, have_k = false, have_v = false, have_proj = false;

@@ -73,7 +73,7 @@ def test_hpsi_c1_all_k(prec, tol, variant):
     print("C1 rel err", _compare(h, ref, s, tol))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("cid", [2, 3, 4])
 def test_hpsi_k_subset_all_bands(cid, variant):
     # several tiles of the batch with ragged npw: every 8th..64th k of the full list,
@@ -92,7 +92,7 @@ def test_hpsi_k_subset_all_bands(cid, variant):
         print(cid, prec, "rel err", _compare(h, ref, s, tol))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_hpsi_c2_full_batch_sampled(variant):
     # the benchmarked launch (512 k x 20 bands), checked on sampled k-points
     from paper_2412_01695_amd import mkpw
@@ -104,6 +104,36 @@ def test_hpsi_c2_full_batch_sampled(variant):
     ks = list(range(0, cfg.nk, 37)) + [cfg.nk - 1]
     ref = _oracle_rows(cfg, s, ham.vtilde(s.vloc), psi, ks)
     print("C2 full rel err", _compare(h, ref, s, TOL64))
+
+
+@pytest.mark.parametrize("cid", [2, 4])
+def test_every_variant_and_workgroup_size(cid):
+    # each (variant, workgroup size) kernel the library has for the mesh, at its
+    # default slab, in both precisions; combinations it does not build are
+    # refused with PW_EINVAL
+    from paper_2412_01695_amd import mkpw
+    cfg0 = synth.make_config(cid)
+    cfg = synth.subset(cfg0, np.arange(0, cfg0.nk, max(1, cfg0.nk // 12)))
+    torch, s = _system(cfg)
+    psi = s.psi_guess()
+    vt = ham.vtilde(s.vloc)
+    ref = _oracle_rows(cfg, s, vt, psi, range(0, cfg.nk, 2))
+    ran = 0
+    for variant in (1, 2):
+        for threads in (256, 512, 1024):
+            mkpw.pw_set_option(s.ctx, "hpsi_variant", variant)
+            mkpw.pw_set_option(s.ctx, "hpsi_threads", threads)
+            for prec, tol in ((0, TOL64), (1, TOL32)):
+                try:
+                    h = _run(torch, s, psi, prec)
+                except mkpw.PwError as e:
+                    assert e.status == mkpw.PW_EINVAL and threads > 256, str(e)
+                    continue
+                assert mkpw.pw_get_option(s.ctx, "hpsi_threads_tuned") == threads
+                assert mkpw.pw_get_option(s.ctx, "hpsi_variant_tuned") == variant
+                print(cid, variant, threads, prec, "rel err", _compare(h, ref, s, tol))
+                ran += 1
+    assert ran >= 6
 
 
 def test_free_electron_exact():
@@ -180,7 +210,7 @@ def test_repeatable_bitwise():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("variant", [1, 2])
 def test_slab_widths_agree(variant):
     # every slab width of the lane-pair kernels gives the same result to rounding
     from paper_2412_01695_amd import mkpw
