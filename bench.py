@@ -162,6 +162,10 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--shape", default=None,
+                    help="fix the H|psi> launch shape as variant,threads,slab (e.g. 1,256,10) instead of "
+                         "autotuning, for profiles that must time one known kernel")
+    ap.add_argument("--tune-log", action="store_true", help="print the autotuner's candidate timings to stderr")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one 1 GiB device-to-device copy (a known-size "
                          "reference dispatch for HBM byte counters)")
@@ -188,6 +192,14 @@ def main():
     h32 = torch.empty_like(psi32)
     nkb = cfg.nk * nbnd
     flops_kb, io_kb = algorithmic_work(cfg, sysm.miller, nbnd)
+
+    if args.tune_log:
+        mkpw.pw_set_option(sysm.ctx, "tune_log", 1)
+    if args.shape:
+        sv = [int(x) for x in args.shape.split(",")]
+        mkpw.pw_set_option(sysm.ctx, "hpsi_variant", sv[0])
+        mkpw.pw_set_option(sysm.ctx, "hpsi_threads", sv[1])
+        mkpw.pw_set_option(sysm.ctx, "hpsi_slab", sv[2])
 
     def shape():
         return {k: mkpw.pw_get_option(sysm.ctx, f"hpsi_{k}_tuned") for k in ("variant", "slab", "threads")}

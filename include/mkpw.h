@@ -73,13 +73,15 @@ const char* pw_last_error(const pw_ctx* ctx);
  * per line, even meshes only), "hpsi_slab" (0 = autotuned, else the number of z planes
  * transformed together) and "hpsi_threads" (0 = autotuned, else 256, 512 or
  * 1024 work-items per workgroup where the kernel fits in the registers
- * that leaves; PW_EINVAL otherwise).  Any nonzero shape option
- * fixes the shape: the others default to variant 1, 256 work-items and the
- * widest slab that fits. */
+ * that leaves; PW_EINVAL otherwise).  Any nonzero shape option fixes the
+ * shape: the others default to variant 1, 256 work-items and the widest slab
+ * that fits.
+ * "tune_log" (nonzero: print each autotuning candidate's time to stderr). */
 pw_status pw_set_option(pw_ctx* ctx, const char* key, int64_t value);
 
 /* Read an option (the keys above), or "hpsi_variant_tuned" / "hpsi_slab_tuned" /
- * "hpsi_threads_tuned" (the shape of this context's last H|psi> launch, 0 if none),
+ * "hpsi_threads_tuned" (the shape of this context's last H|psi> launch, 0 if
+ * none),
  * or "device_bytes" (device memory the context holds now). */
 pw_status pw_get_option(const pw_ctx* ctx, const char* key, int64_t* value);
 

@@ -241,6 +241,8 @@ pw_status pw_set_option(pw_ctx* c, const char* key, int64_t value) {
     if (value != 0 && value != 256 && value != 512 && value != 1024)
       return set_err(c, PW_EINVAL, "hpsi_threads must be 0, 256, 512 or 1024");
     c->hpsi_threads = value;
+  } else if (k == "tune_log") {
+    c->tune_log = value;
   } else {
     return set_err(c, PW_EINVAL, "unknown option '" + k + "'");
   }
@@ -259,6 +261,7 @@ pw_status pw_get_option(const pw_ctx* c, const char* key, int64_t* value) {
   else if (k == "hpsi_threads") *value = c->hpsi_threads;
   else if (k == "hpsi_slab_tuned") *value = c->last_hpsi_slab;
   else if (k == "hpsi_threads_tuned") *value = c->last_hpsi_threads;
+  else if (k == "tune_log") *value = c->tune_log;
   else if (k == "device_bytes") {
     int64_t b = 0;
     for (auto& m : c->owned) b += (int64_t)m.bytes;

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <string>
@@ -70,6 +71,20 @@ __device__ __forceinline__ int lane_half(int h) {
   return h;
 }
 
+// LDS pointers carry their address space, so that index arithmetic on them
+// is 32-bit; complex values are moved through them member by member.
+template <class U>
+using lds_t = __attribute__((address_space(3))) U;
+template <class T>
+__device__ __forceinline__ cplx<T> lds_ld(const lds_t<cplx<T>>* p) {
+  return {p->x, p->y};
+}
+template <class T>
+__device__ __forceinline__ void lds_st(lds_t<cplx<T>>* p, cplx<T> v) {
+  p->x = v.x;
+  p->y = v.y;
+}
+
 // Per-row context.
 template <class T>
 struct Row {
@@ -114,32 +129,33 @@ __device__ __forceinline__ bool row_of_block(const KTables& t, const VecSel& sel
 // gamma_p = sum_q D_pq lambda_q (Eq. gamma), lambda_q summed over the nslot
 // per-wave partial sums in red[w][q]; D is staged in LDS (dl[p][q]).
 template <class T>
-__device__ __forceinline__ void finish_gamma(int p, int nproj, const cplx<T>* dl, const cplx<T>* red, int nslot,
-                                             cplx<T>* gam) {
+__device__ __forceinline__ void finish_gamma(int p, int nproj, const lds_t<cplx<T>>* dl, const lds_t<cplx<T>>* red,
+                                             int nslot, lds_t<cplx<T>>* gam) {
   cplx<T> g = {T(0), T(0)};
   for (int q = 0; q < nproj; ++q) {
     cplx<T> lam = {T(0), T(0)};
-    for (int w = 0; w < nslot; ++w) lam = cadd(lam, red[w * nproj + q]);
-    g = cadd(g, cmul(dl[p * nproj + q], lam));
+    for (int w = 0; w < nslot; ++w) lam = cadd(lam, lds_ld(red + w * nproj + q));
+    g = cadd(g, cmul(lds_ld(dl + p * nproj + q), lam));
   }
-  gam[p] = g;
+  lds_st(gam + p, g);
 }
 
 // Gather the local term from the sticks and add (1/2)|k+G|^2 psi and
 // sum_q gamma_q beta_q (Eq. finalnl); the padding of the row is written as zero.
 template <class T, int ZS, int NT>
-__device__ __forceinline__ void gather_add(const Row<T>& r, int nproj, const cplx<T>* Z, const cplx<T>* gam) {
+__device__ __forceinline__ void gather_add(const Row<T>& r, int nproj, const lds_t<cplx<T>>* Z,
+                                           const lds_t<cplx<T>>* gam) {
   const cplx<T> zero = {T(0), T(0)};
   for (int g = threadIdx.x; g < r.npwx; g += NT) {
     cplx<T> h = zero;
     if (g < r.npw) {
       int gm = r.gmap[g];
-      h = Z[(gm >> 8) * ZS + (gm & 255)];
+      h = lds_ld(Z + (gm >> 8) * ZS + (gm & 255));
       cplx<T> v = r.p[g];
       T kk = (T)r.kin[g];
       h.x += kk * v.x;
       h.y += kk * v.y;
-      for (int q = 0; q < nproj; ++q) h = cadd(h, cmul(r.bk[(long)q * r.npwx + g], gam[q]));
+      for (int q = 0; q < nproj; ++q) h = cadd(h, cmul(r.bk[(long)q * r.npwx + g], lds_ld(gam + q)));
     }
     r.hp[g] = h;
   }
@@ -147,16 +163,22 @@ __device__ __forceinline__ void gather_add(const Row<T>& r, int nproj, const cpl
 
 // ---------------------------------------------------------------- 1D passes
 // Each pass comes in a one-work-item-per-line form and, for even N, a
-// lane-pair form (pair_inverse / pair_forward in fft.hpp).
+// lane-pair form (pair_inverse / pair_forward in fft.hpp).  The callbacks
+// work on register slots: inverse outputs go to st(J, v) for slot J, which is
+// point J of the line (one work-item) or point 2 J + h (lane h of a pair);
+// forward inputs come from ld(J) for the same slots; forward outputs go to
+// st(K, v), K < min(WC, N/2) for a pair, which is coefficient K or K + h N/2.
+// The callers turn slots into addresses with per-lane bases and uniform
+// strides.
 
-// inverse along one line: WC inputs from ld(m) -> N outputs to st(l, value)
+// inverse along one line: WC inputs from ld(m) -> N outputs
 template <class T, int N, int WC, bool PAIR, class LD, class ST>
 __device__ __forceinline__ void line_inverse(int h, LD&& ld, ST&& st) {
   if constexpr (PAIR) {
     constexpr int M = N / 2;
     cplx<T> v[M];
     pair_inverse<T, N, WC, +1>(v, h, ld);
-    sfor<M>([&](auto j) { st(2 * decltype(j)::value + h, v[decltype(j)::value]); });
+    sfor<M>([&](auto j) { st(decltype(j)::value, v[decltype(j)::value]); });
   } else {
     cplx<T> v[N];
     sfor<N>([&](auto j) {
@@ -169,16 +191,16 @@ __device__ __forceinline__ void line_inverse(int h, LD&& ld, ST&& st) {
   }
 }
 
-// forward along one line: N inputs from ld(l) -> the first WC outputs to st(m, value)
+// forward along one line: N inputs -> the first WC outputs
 template <class T, int N, int WC, bool PAIR, class LD, class ST>
 __device__ __forceinline__ void line_forward(int h, LD&& ld, ST&& st) {
   if constexpr (PAIR) {
     constexpr int M = N / 2;
     constexpr int KO = WC < M ? WC : M;
     cplx<T> v[M];
-    sfor<M>([&](auto j) { v[decltype(j)::value] = ld(2 * decltype(j)::value + h); });
+    sfor<M>([&](auto j) { v[decltype(j)::value] = ld(decltype(j)::value); });
     pair_forward<T, N, WC, -1>(v, h);
-    sfor<KO>([&](auto k) { st(decltype(k)::value + h * M, v[decltype(k)::value]); });
+    sfor<KO>([&](auto k) { st(decltype(k)::value, v[decltype(k)::value]); });
   } else {
     cplx<T> v[N];
     sfor<N>([&](auto j) { v[decltype(j)::value] = ld(decltype(j)::value); });
@@ -187,8 +209,8 @@ __device__ __forceinline__ void line_forward(int h, LD&& ld, ST&& st) {
   }
 }
 
-// x line: WC inputs -> N points -> * V/N_r -> forward -> WC outputs.  vat(J)
-// gives V at the J-th point the work-item holds: point J, or 2 J + h of a pair.
+// x line: WC inputs -> N points -> * V/N_r -> forward -> WC outputs; vat(J)
+// gives V at the point of slot J
 template <class T, int N, int WC, bool PAIR, class LD, class VAT, class ST>
 __device__ __forceinline__ void line_xv(int h, LD&& ld, VAT&& vat, ST&& st) {
   if constexpr (PAIR) {
@@ -198,12 +220,12 @@ __device__ __forceinline__ void line_xv(int h, LD&& ld, VAT&& vat, ST&& st) {
     pair_inverse<T, N, WC, +1>(v, h, ld);
     sfor<M>([&](auto j) {
       constexpr int J = decltype(j)::value;
-      T f = vat(J);  // point 2 J + h of the line
+      T f = vat(J);
       v[J].x *= f;
       v[J].y *= f;
     });
     pair_forward<T, N, WC, -1>(v, h);
-    sfor<KO>([&](auto k) { st(decltype(k)::value + h * M, v[decltype(k)::value]); });
+    sfor<KO>([&](auto k) { st(decltype(k)::value, v[decltype(k)::value]); });
   } else {
     cplx<T> v[N];
     sfor<N>([&](auto j) {
@@ -223,6 +245,23 @@ __device__ __forceinline__ void line_xv(int h, LD&& ld, VAT&& vat, ST&& st) {
   }
 }
 
+// Global loads through a buffer descriptor: a per-lane byte offset plus a
+// wave-uniform one, so that strided loads cost no vector address arithmetic.
+// Offsets past num_records read as zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+template <class T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // ---------------------------------------------------------------- the kernel
 // LDS layout of one workgroup, in elements of cplx<T> unless noted.
 struct HpsiLds {
@@ -234,11 +273,11 @@ __host__ __device__ inline HpsiLds hpsi_lds_layout(int smax, int wx, int l3c, in
   const int np = nproj > 0 ? nproj : 1;
   HpsiLds L;
   L.z = (size_t)(smax + 2) * (N | 1);  // sticks, then one zero row and one write-sink row
-  L.y = (size_t)l3c * N * (wx | 1);    // slab planes
+  L.y = (size_t)l3c * wx * (N | 1);    // slab planes: [l3c][wx][N | 1]
   L.red = (size_t)(threads / 64) * np; // per-wave projector partial sums
   L.gam = np;
   L.dl = (size_t)np * np;
-  L.sof_bytes = ((size_t)wx * WC * sizeof(short) + 15) / 16 * 16;
+  L.sof_bytes = (size_t)2 * wx * WC * sizeof(int);  // stick row offsets for reads and for writes
   L.bytes = (L.z + L.y + L.red + L.gam + L.dl) * cs + L.sof_bytes;
   return L;
 }
@@ -253,8 +292,8 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
                                                   const cplx<T>* __restrict__ dij,
                                                   const T* __restrict__ vr,
                                                   const cplx<T>* __restrict__ psi,
-                                                  cplx<T>* __restrict__ hpsi, int l3c, int ys,
-                                                  int per_xcd, int ntask) {
+                                                  cplx<T>* __restrict__ hpsi, int l3c, int per_xcd,
+                                                  int ntask) {
   static_assert(!(ZYP || XP) || N % 2 == 0, "lane-pair passes need an even length");
   Row<T> r;
   if (!row_of_block(t, sel, nproj, beta, psi, hpsi, per_xcd, ntask, r)) return;
@@ -266,12 +305,18 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
 
   const HpsiLds L = hpsi_lds_layout<T, N, WC>(t.smax, wx, l3c, nproj, NT);
   extern __shared__ __align__(16) unsigned char smem[];
-  cplx<T>* Z = reinterpret_cast<cplx<T>*>(smem);  // [smax + 2][ZS]
-  cplx<T>* Y = Z + L.z;                           // [l3c][N][ys], ys odd >= wx
-  cplx<T>* red = Y + L.y;                         // [NW][nproj]
-  cplx<T>* gam = red + L.red;                     // [nproj]
-  cplx<T>* dl = gam + L.gam;                      // [nproj][nproj]
-  short* sof = reinterpret_cast<short*>(dl + L.dl);  // [wx][WC] stick of (m1', m2'), zrow if none
+  typedef lds_t<cplx<T>> lc;
+  lc* Z = (lc*)smem;     // [smax + 2][ZS]
+  lc* Y = Z + L.z;       // [l3c][wx][YS]: the y lines of the slab's occupied x columns
+  lc* red = Y + L.y;     // [NW][nproj]
+  lc* gam = red + L.red;  // [nproj]
+  lc* dl = gam + L.gam;   // [nproj][nproj]
+  // byte offset in Z of the stick of (m1', m2'), [wx][WC]: the zero row where
+  // there is none (for reads), the write-only row (for writes)
+  lds_t<int>* sofr = (lds_t<int>*)(dl + L.dl);
+  lds_t<int>* sofw = sofr + wx * WC;
+  constexpr int YS = N | 1;  // y-line stride in Y (odd: no bank aliasing between columns)
+  constexpr int CS = (int)sizeof(cplx<T>);
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -303,15 +348,16 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
   // ---- 1. zero the stick windows and the zero row, stage the stick map and D
   for (int i = tid; i < ns * WC; i += NT) {
     int s = i / WC, j = i - s * WC;
-    Z[s * ZS + j] = zero;
+    lds_st(Z + s * ZS + j, zero);
   }
-  for (int i = tid; i < N; i += NT) Z[zrow * ZS + i] = zero;
+  for (int i = tid; i < N; i += NT) lds_st(Z + zrow * ZS + i, zero);
   for (int i = tid; i < wx * WC; i += NT) {
     const int m1 = i / WC, m2 = i - m1 * WC;
     int s = m2 < wy ? r.sof[m1 * wy + m2] : -1;
-    sof[i] = (short)(s >= 0 ? s : zrow);
+    sofr[i] = (s >= 0 ? s : zrow) * ZS * CS;
+    sofw[i] = (s >= 0 ? s : sink) * ZS * CS;
   }
-  for (int i = tid; i < nproj * nproj; i += NT) dl[i] = dij[i];
+  for (int i = tid; i < nproj * nproj; i += NT) lds_st(dl + i, dij[i]);
   __syncthreads();
 
   // ---- 2. scatter psi into the sticks; the same loads give the partial
@@ -328,7 +374,7 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
       for (int q = 0; q < kProjChunk; ++q) {
         if (q0 + q < nproj) {
           const T sx = wave_sum(ax[q]), sy = wave_sum(ay[q]);
-          if (lane == 0) red[wave * nproj + q0 + q] = {sx, sy};
+          if (lane == 0) lds_st(red + wave * nproj + q0 + q, cplx<T>{sx, sy});
         }
       }
     };
@@ -337,7 +383,7 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       if (tid + u * NT < r.npw) {
-        Z[(gv[u] >> 8) * ZS + (gv[u] & 255)] = pv[u];
+        lds_st(Z + (gv[u] >> 8) * ZS + (gv[u] & 255), pv[u]);
 #pragma unroll
         for (int q = 0; q < kProjChunk; ++q)
           if (q < npre) acc(q, bv[u][q], pv[u]);
@@ -346,7 +392,7 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
     for (int g = tid + kPre * NT; g < r.npw; g += NT) {
       const cplx<T> v = r.p[g];
       const int gm = r.gmap[g];
-      Z[(gm >> 8) * ZS + (gm & 255)] = v;
+      lds_st(Z + (gm >> 8) * ZS + (gm & 255), v);
 #pragma unroll
       for (int q = 0; q < kProjChunk; ++q)
         if (q < npre) acc(q, r.bk[(long)q * r.npwx + g], v);
@@ -374,8 +420,10 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
     if (wave < zwaves) {
       for (int s = zy_slot; s < ns; s += (ZYP ? zwaves * 32 : zwaves * 64)) {
         const int h = lane_half(h0);
-        cplx<T>* zr = Z + s * ZS;
-        line_inverse<T, N, WC, ZYP>(h, [&](int m) { return zr[m]; }, [&](int l, cplx<T> v) { zr[l] = v; });
+        lc* zr = Z + s * ZS;
+        lc* zh = zr + (ZYP ? h : 0);
+        line_inverse<T, N, WC, ZYP>(
+            h, [&](int m) { return lds_ld(zr + m); }, [&](int j, cplx<T> v) { lds_st(zh + (ZYP ? 2 : 1) * j, v); });
       }
     }
     // read by the gather; the barriers of the slab loop publish it
@@ -385,29 +433,37 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
 
   // ---- 4. slabs of z planes.  V is stored permuted per slab so that the
   //         x-line work-items of a slab read it contiguously: Vp[slab][l1][lc][l2].
+  const __amdgpu_buffer_rsrc_t vres = make_rsrc(vr, N * N * N * (int)sizeof(T));
   for (int l30 = 0; l30 < N; l30 += l3c) {
     const int nl = min(l3c, N - l30);
-    const T* vslab = vr + (size_t)l30 * N * N;
+    const int vbase = l30 * N * N * (int)sizeof(T);  // byte offset of the slab in V
     // inverse y on the occupied columns m1' < wx: W inputs (from the sticks) -> N outputs
     for (int i = zy_slot; i < wx * nl; i += kZyStride) {
       const int h = lane_half(h0);
-      const int lc = i / wx, m1 = i - lc * wx, l3 = l30 + lc;
-      cplx<T>* y = Y + (size_t)lc * N * ys + m1;
-      const short* so = sof + m1 * WC;
+      const int lcn = i / wx, m1 = i - lcn * wx, l3 = l30 + lcn;
+      lc* yh = Y + i * YS + (ZYP ? h : 0);  // i = lc wx + m1
+      const lds_t<int>* so = sofr + m1 * WC;
+      const lds_t<char>* zl = (const lds_t<char>*)(Z + l3);
       line_inverse<T, N, WC, ZYP>(
-          h, [&](int m) { return Z[so[m] * ZS + l3]; }, [&](int l, cplx<T> v) { y[l * ys] = v; });
+          h, [&](int m) { return lds_ld((const lc*)(zl + so[m])); },
+          [&](int j, cplx<T> v) { lds_st(yh + (ZYP ? 2 : 1) * j, v); });
     }
     __syncthreads();
     // x lines: W inputs -> N points -> * V/N_r -> forward -> W outputs
     for (int i = x_slot; i < N * nl; i += kXStride) {
       const int h = lane_half(h0);
-      cplx<T>* y = Y + (size_t)i * ys;  // i = lc * N + l2
-      const T* vv = vslab + i;
+      const int lcn = i / N, l2 = i - lcn * N;  // i = lc N + l2
+      lc* y = Y + lcn * wx * YS + l2;
+      const int mo = XP ? h * (N / 2) : 0;
+      lc* yo = y + mo * YS;
+      // V at point l1 of this line: byte vbase + ((l1 nl + lc) N + l2) sizeof(T)
+      const int voff = (i + (XP ? h : 0) * nl * N) * (int)sizeof(T);
+      const int vstep = (XP ? 2 : 1) * nl * N * (int)sizeof(T);
       line_xv<T, N, WC, XP>(
-          h, [&](int m) { return m < wx ? y[m] : zero; },
-          [&](int j) { return vv[(size_t)(XP ? 2 * j + h : j) * nl * N]; },
-          [&](int m, cplx<T> v) {
-            if (m < wx) y[m] = v;
+          h, [&](int m) { return m < wx ? lds_ld(y + m * YS) : zero; },
+          [&](int j) { return buf_load<T>(vres, voff, vbase + j * vstep); },
+          [&](int k, cplx<T> v) {
+            if (k + mo < wx) lds_st(yo + k * YS, v);
           });
     }
     __syncthreads();
@@ -415,16 +471,16 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
     // stick go to the write-only row)
     for (int i = zy_slot; i < wx * nl; i += kZyStride) {
       const int h = lane_half(h0);
-      const int lc = i / wx, m1 = i - lc * wx, l3 = l30 + lc;
-      const cplx<T>* y = Y + (size_t)lc * N * ys + m1;
-      const short* so = sof + m1 * WC;
+      const int lcn = i / wx, m1 = i - lcn * wx, l3 = l30 + lcn;
+      const lc* yh = Y + i * YS + (ZYP ? h : 0);
+      const int mo = ZYP ? h * (N / 2) : 0;
+      const lds_t<int>* so = sofw + m1 * WC + mo;
+      lds_t<char>* zl = (lds_t<char>*)(Z + l3);
       line_forward<T, N, WC, ZYP>(
-          h, [&](int l) { return y[l * ys]; },
-          [&](int m2, cplx<T> v) {
-            if (m2 < WC) {  // the second lane of a pair also returns outputs M.. of the line
-              const int s = so[m2];
-              Z[(s == zrow ? sink : s) * ZS + l3] = v;
-            }
+          h, [&](int j) { return lds_ld(yh + (ZYP ? 2 : 1) * j); },
+          [&](int k, cplx<T> v) {
+            // the second lane of a pair also returns outputs N/2.. of the line
+            if (k + mo < WC) lds_st((lc*)(zl + so[k]), v);
           });
     }
     __syncthreads();
@@ -433,11 +489,12 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
   // ---- 5. forward z on the sticks: N inputs -> W outputs (in place)
   for (int s = zy_slot; s < ns; s += kZyStride) {
     const int h = lane_half(h0);
-    cplx<T>* zr = Z + s * ZS;
+    lc* zr = Z + s * ZS;
+    const int mo = ZYP ? h * (N / 2) : 0;
     line_forward<T, N, WC, ZYP>(
-        h, [&](int l) { return zr[l]; },
-        [&](int m3, cplx<T> v) {
-          if (m3 < WC) zr[m3] = v;
+        h, [&](int j) { return lds_ld(zr + (ZYP ? 2 * j + h : j)); },
+        [&](int k, cplx<T> v) {
+          if (k + mo < WC) lds_st(zr + mo + k, v);
         });
   }
   __syncthreads();
@@ -521,7 +578,6 @@ const void* hpsi_kernel_ptr(const HpsiShape& sh) {
 template <class T, int N, int WC>
 pw_status launch_shape(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st, HpsiShape sh) {
   KTables t = c->tables();
-  const int ys = t.wx | 1;
   const int l3c = sh.l3c;
   const int nproj_k = c->have_proj ? c->nproj : 0;
   const size_t lds = hpsi_lds<T, N, WC>(t, l3c, nproj_k, sh.threads);
@@ -554,9 +610,9 @@ pw_status launch_shape(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi
   const T* vpt = (const T*)vp;
   const cplx<T>* pin = (const cplx<T>*)psi;
   cplx<T>* pout = (cplx<T>*)hpsi;
-  int l3c_arg = l3c, ys_arg = ys, ntask_arg = (int)ntask;
+  int l3c_arg = l3c, ntask_arg = (int)ntask;
   VecSel sel_arg = sel;
-  void* args[] = {&t, &sel_arg, &nproj, &beta, &dij, &vpt, &pin, &pout, &l3c_arg, &ys_arg, &per_xcd, &ntask_arg};
+  void* args[] = {&t, &sel_arg, &nproj, &beta, &dij, &vpt, &pin, &pout, &l3c_arg, &per_xcd, &ntask_arg};
   hipError_t e = hipLaunchKernel(kern, dim3(8u * (unsigned)per_xcd), dim3(sh.threads), args, lds, st);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return set_err(c, PW_EDEVICE, std::string("h_psi launch: ") + hipGetErrorString(e));
@@ -672,6 +728,9 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
       float ms = 0.f;
       if (!time_it(cands[i], 2, &ms)) break;
       t1.push_back({ms, i});
+      if (c->tune_log)
+        fprintf(stderr, "hpsi tune fp%d N=%d WC=%d variant=%d threads=%d slab=%d: %.4f ms\n", (int)sizeof(T) * 8,
+                N, WC, cands[i].variant, cands[i].threads, cands[i].l3c, ms);
     }
     if (s == PW_OK) {
       std::sort(t1.begin(), t1.end());

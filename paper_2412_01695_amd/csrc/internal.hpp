@@ -109,6 +109,7 @@ struct pw_ctx {
   int64_t hpsi_variant = 0;  // 0 = autotuned, else the kernel variant (1, 2)
   int64_t hpsi_slab = 0;     // 0 = autotuned, else z planes per slab
   int64_t hpsi_threads = 0;  // 0 = autotuned, else work-items per workgroup
+  int64_t tune_log = 0;      // print the autotuning timings to stderr
   int last_hpsi_variant = 0, last_hpsi_slab = 0, last_hpsi_threads = 0;  // shape of the last H|psi> launch
 
   // crystal and basis

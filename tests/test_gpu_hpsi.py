@@ -219,7 +219,7 @@ def test_slab_widths_agree(variant):
     psi = s.psi_guess()
     mkpw.pw_set_option(s.ctx, "hpsi_variant", variant)
     outs = []
-    for slab in (1, 3, 7, 24):
+    for slab in (1, 3, 7, 12, 24):
         mkpw.pw_set_option(s.ctx, "hpsi_slab", slab)
         outs.append(_run(torch, s, psi, 0))
     for o in outs[1:]:
