@@ -171,6 +171,11 @@ __device__ __forceinline__ void bfly_odd(cplx<T> (&a)[R]) {
   a[0] = x0;
 }
 
+template <class T, int N, int SIGN>
+__device__ __forceinline__ void fft(cplx<T> (&x)[N]);
+
+// a radix-R butterfly is an R-point DFT: 2 and 4 written out, odd primes by
+// the symmetric form above, composite radices (8) by the recursion
 template <class T, int R, int SIGN>
 __device__ __forceinline__ void bfly(cplx<T> (&a)[R]) {
   if constexpr (R == 1) {
@@ -178,15 +183,24 @@ __device__ __forceinline__ void bfly(cplx<T> (&a)[R]) {
     bfly2<T, SIGN>(a);
   } else if constexpr (R == 4) {
     bfly4<T, SIGN>(a);
-  } else {
-    static_assert(R % 2 == 1, "odd radix expected");
+  } else if constexpr (R == 3 || R == 5 || R == 7) {
     bfly_odd<T, R, SIGN>(a);
+  } else {
+    fft<T, R, SIGN>(a);
   }
 }
 
-template <int N>
+// First radix of the decimation-in-time split.  Inverse transforms here
+// always start from a window of nonzero inputs and forward ones always end in
+// a window of wanted outputs; for 24, 30 and 36 points a different first
+// split lets the most operations on the zeros (or on the unwanted outputs)
+// fold away in each direction (chosen by counting the generated instructions).
+template <int N, int SIGN>
 constexpr int pick_radix() {
-  if constexpr (N == 1 || N == 2 || N == 3 || N == 4 || N == 5) return N;
+  if constexpr (N == 24) return SIGN > 0 ? 8 : 3;
+  else if constexpr (N == 30) return SIGN > 0 ? 3 : 5;
+  else if constexpr (N == 36) return 3;
+  else if constexpr (N == 1 || N == 2 || N == 3 || N == 4 || N == 5) return N;
   else if constexpr (N % 4 == 0) return 4;
   else if constexpr (N % 2 == 0) return 2;
   else if constexpr (N % 3 == 0) return 3;
@@ -197,7 +211,7 @@ constexpr int pick_radix() {
 // In-place length-N DFT of x (decimation in time, fully unrolled).
 template <class T, int N, int SIGN>
 __device__ __forceinline__ void fft(cplx<T> (&x)[N]) {
-  constexpr int R = pick_radix<N>();
+  constexpr int R = pick_radix<N, SIGN>();
   if constexpr (R == N) {
     bfly<T, N, SIGN>(x);
   } else {
