@@ -121,6 +121,62 @@ def time_davidson(torch, mkpw, sysm, prec, tol_ry):
             "iters_max": int(iters.max()), "tol_ry": tol_ry}, eig
 
 
+def dfpt_sample(torch, mkpw, cfg_id, thr=1e-24):
+    """Batched DFPT CG on a whole workload: occupied states from an FP64
+    Davidson, rhs = -(1 - P_v) dV u with dV u taken as (T + dV) u - T u from a
+    second context whose local potential is dV, then (H - eps + alpha P_v) x =
+    rhs for every (k, occupied band) in one pw_dfpt_cg call, FP64 and mixed.
+    The accuracy check applies A once more through pw_h_psi."""
+    from paper_2412_01695_amd import synth
+    from paper_2412_01695_amd.system import System
+
+    cfg = synth.make_config(cfg_id)
+    nocc = int(cfg.extra.get("nocc", cfg.nbnd))
+    sysm = System(cfg, 0)
+    dsys = System(cfg, 0, stream=sysm.stream, vloc=synth.dv_grid(cfg, int(cfg.extra.get("dv_seed", 7))),
+                  with_projectors=False)
+    torch.cuda.set_stream(sysm.stream)
+    try:
+        u = torch.from_numpy(sysm.psi_guess(nocc)).cuda()
+        st, eig, iters, conv = mkpw.pw_davidson(sysm.ctx, mkpw.PW_FP64, nocc, u, cfg.nk, 1e-10, 300)
+        # kinetic 1/2 |k+G|^2 in the library's plane-wave order, zero on the padding
+        kin = np.zeros((cfg.nk, 1, sysm.npwx))
+        for ik, m in enumerate(sysm.miller):
+            q = synth.q_vectors(cfg, ik, m)
+            kin[ik, 0, :m.shape[0]] = 0.5 * np.einsum("ij,ij->i", q, q)
+        kin = torch.from_numpy(kin).cuda()
+        tu = torch.empty_like(u)
+        mkpw.pw_h_psi(dsys.ctx, mkpw.PW_FP64, nocc, u, tu)
+        dvu = tu - kin * u
+        c = torch.bmm(u.conj(), dvu.transpose(1, 2).contiguous())           # [k, mu, nu] = <u_mu|dV u_nu>
+        rhs = -(dvu - torch.bmm(c.transpose(1, 2).contiguous(), u))          # -(1 - P_v) dV u
+        eps = np.ascontiguousarray(eig)
+        alpha = np.maximum(2.0 * (eps.max(axis=1) - eps.min(axis=1)), 0.1)
+        out = {"workload": f"{cfg.name}: {cfg.nk} k, {nocc} occupied bands = rhs per k, FFT {cfg.fft[0]}^3, "
+                           f"{cfg.nproj} projectors; occupied states from FP64 Davidson ({int(conv.sum())}/{cfg.nk} "
+                           f"k converged)", "systems": cfg.nk * nocc, "thr": thr}
+        eps_t = torch.from_numpy(eps).cuda()[:, :, None]
+        a_t = torch.from_numpy(alpha).cuda()[:, None, None]
+        for name, prec in (("fp64", mkpw.PW_FP64), ("mixed", mkpw.PW_MIXED)):
+            x = torch.zeros_like(rhs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, it = mkpw.pw_dfpt_cg(sysm.ctx, prec, nocc, u, eps, alpha, nocc, rhs, x, thr, 2000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            hx = torch.empty_like(x)
+            mkpw.pw_h_psi(sysm.ctx, mkpw.PW_FP64, nocc, x, hx)
+            ux = torch.bmm(u.conj(), x.transpose(1, 2).contiguous())
+            ax = hx - eps_t * x + a_t * torch.bmm(ux.transpose(1, 2).contiguous(), u)
+            rel = (torch.linalg.vector_norm(ax - rhs, dim=2) / torch.linalg.vector_norm(rhs, dim=2)).max().item()
+            out[name] = {"seconds": dt, "status": int(st), "iters_min": int(it.min()), "iters_max": int(it.max()),
+                         "systems_per_s": cfg.nk * nocc / dt, "max_rel_residual": rel}
+        return out
+    finally:
+        dsys.close()
+        sysm.close()
+
+
 def serving_sample(n, rate=20.0):
     from paper_2412_01695_amd import serve
     reqs = serve.make_requests(n, rate)
@@ -161,6 +217,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--dfpt-config", type=int, default=3, help="workload of the DFPT CG sample (0: skip)")
     ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--shape", default=None,
                     help="fix the H|psi> launch shape as variant,threads,slab (e.g. 1,256,10) instead of "
@@ -273,6 +330,8 @@ def main():
                 res["solve"][name]["max_eig_err_vs_oracle_ry"] = err[name]
             res["solve"]["oracle_k_sample"] = ks
     sysm.close()
+    if args.dfpt_config > 0:
+        res["dfpt"] = dfpt_sample(torch, mkpw, args.dfpt_config)
     if args.serve_requests > 0:
         res["serving"] = serving_sample(args.serve_requests)
     print(json.dumps(res))

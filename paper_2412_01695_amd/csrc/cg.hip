@@ -12,9 +12,11 @@
 //   M_GG = max(1, (|k+G|^2/2) / <u_nu|T|u_nu>)   (Sec. 2.4 preconditioner)
 // The paper keeps rho, gamma and lambda on the CPU; here every scalar stays
 // on the device and the host only reads the per-system "active" flags.
-// Mixed precision applies H in complex64 (everything else FP64) until
-// convergence, then recomputes r = A x - b with H in FP64 and continues: the
-// FP32 phase does the bulk of the work and the FP64 phase removes its error.
+// Mixed precision applies H in complex64 (everything else FP64) until each
+// system's residual has dropped by a fixed factor (or below thr), then
+// recomputes r = A x - b with H in FP64 and continues to thr: the FP32 phase
+// does the bulk of the work and the FP64 phase removes its error.  H is only
+// applied to the systems still active.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,10 +80,12 @@ __global__ __launch_bounds__(256) void init_resid_kernel(const cd* t, const cd* 
   if (threadIdx.x == 0) active[sys] = 1;
 }
 
-// d = M^-1 r, rho = Re(d^H r); convergence; gamma step from the 2nd iteration
+// d = M^-1 r, rho = Re(d^H r); convergence when |rho| < max(thr, rel |rho at the
+// phase's first iteration|); gamma step from the 2nd iteration
 __global__ __launch_bounds__(256) void step1_kernel(const cd* r, cd* d, const cd* dold, const double* kin,
                                                     const double* tk, const int* npw, int npwx, int nrhs, double* rho,
-                                                    double* rho_old, int* active, int first, double thr) {
+                                                    double* rho_old, double* rho0, int* active, int first, double thr,
+                                                    double rel) {
   const long sys = blockIdx.x;
   if (!active[sys]) return;
   const int k = (int)(sys / nrhs);
@@ -95,7 +99,8 @@ __global__ __launch_bounds__(256) void step1_kernel(const cd* r, cd* d, const cd
     s += v.x * r[o + g].x + v.y * r[o + g].y;
   }
   s = block_sum2(s, red);
-  if (fabs(s) < thr) {
+  if (first && threadIdx.x == 0) rho0[sys] = s;
+  if (fabs(s) < fmax(thr, rel * fabs(first ? s : rho0[sys]))) {
     if (threadIdx.x == 0) {
       active[sys] = 0;
       rho[sys] = s;
@@ -179,6 +184,11 @@ struct Buf2 {
 
 }  // namespace
 
+// rho reduction (squared M^-1-norm of the residual) at which the mixed mode
+// leaves complex64 H: a residual norm 1e-5 of the starting one, near what an
+// H application with FP32 rounding (relative error ~1e-6) can still resolve
+constexpr double kRelFp32 = 1e-10;
+
 pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const double* eps_h, const double* alpha_h,
                       int nrhs, const cd* b, cd* x, double thr, int max_iter, int32_t* iters_out) {
   hipStream_t st = c->stream;
@@ -198,6 +208,8 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
   CTRY(bf.get((size_t)nk, &alpha));
   CTRY(bf.get((size_t)nsys, &rho));
   CTRY(bf.get((size_t)nsys, &rho_old));
+  double* rho0;
+  CTRY(bf.get((size_t)nsys, &rho0));
   CTRY(bf.get((size_t)nsys, &tk));
   CTRY(bf.get((size_t)nsys, &active));
   cplx<float>*v32 = nullptr, *t32 = nullptr;
@@ -214,17 +226,17 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
 
   bool fp64_h = prec == PW_FP64;
   // t = H v + alpha U (U^H v) for all systems
-  auto apply_a = [&](const cd* v) -> pw_status {
+  // t = A v; with `live`, H is applied to the active systems only (the others'
+  // t is not read)
+  auto apply_a = [&](const cd* v, const int* live) -> pw_status {
+    VecSel sel;
+    sel.nvec = nrhs;
+    sel.kstride = (long)nrhs * npwx;
+    sel.live = live;
     if (fp64_h) {
-      VecSel sel;
-      sel.nvec = nrhs;
-      sel.kstride = (long)nrhs * npwx;
       CTRY(launch_hpsi(c, PW_FP64, sel, v, t, st));
     } else {
       CTRY(launch_to_c64(c, v, (long)nrhs * npwx, nullptr, v32, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
-      VecSel sel;
-      sel.nvec = nrhs;
-      sel.kstride = (long)nrhs * npwx;
       CTRY(launch_hpsi(c, PW_MIXED, sel, v32, t32, st));
       CTRY(launch_to_c128(c, t32, (long)nrhs * npwx, nullptr, t, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
     }
@@ -246,7 +258,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     return PW_OK;
   };
   auto restart = [&]() -> pw_status {
-    CTRY(apply_a(x));
+    CTRY(apply_a(x, nullptr));
     hipLaunchKernelGGL(init_resid_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, x, b, eps, r, npwx, active,
                        c->d_npw, nrhs);
     return check_launch(c, "init_resid", st);
@@ -258,8 +270,11 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
   bool ok = false;
   int it_total = 0;
   for (int it = 1; it <= max_iter; ++it) {
+    // the FP32 phase of the mixed mode stops at a residual reduction its
+    // H application can still resolve; the FP64 phase runs to thr
+    const double rel = fp64_h ? 0.0 : kRelFp32;
     hipLaunchKernelGGL(step1_kernel, dim3((unsigned)nsys), dim3(256), 0, st, r, d, dold, c->d_kin, tk, c->d_npw,
-                       npwx, nrhs, rho, rho_old, active, first, thr);
+                       npwx, nrhs, rho, rho_old, rho0, active, first, thr, rel);
     CTRY(check_launch(c, "cg_step1", st));
     CHIP(c, hipMemcpyAsync(act.data(), active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
     CHIP(c, hipStreamSynchronize(st));
@@ -283,7 +298,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
       break;
     }
     first = 0;
-    CTRY(apply_a(d));
+    CTRY(apply_a(d, active));
     hipLaunchKernelGGL(step2_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, d, dold, x, r, eps, c->d_npw, npwx,
                        nrhs, rho, rho_old, active);
     CTRY(check_launch(c, "cg_step2", st));

@@ -111,6 +111,7 @@ __device__ __forceinline__ bool row_of_block(const KTables& t, const VecSel& sel
   const int iv = task - ik * sel.nvec;
   const int cnt = sel.cnt ? sel.cnt[ik] : sel.nvec;
   if (iv >= cnt) return false;
+  if (sel.live && !sel.live[task]) return false;
   const int off = sel.off ? sel.off[ik] : 0;
   r.ik = ik;
   r.npwx = t.npwx;

@@ -36,6 +36,7 @@ struct VecSel {
   long kstride = 0;         // elements between consecutive k
   const int* off = nullptr; // [nk] or null
   const int* cnt = nullptr; // [nk] or null
+  const int* live = nullptr;  // [nk * nvec] nonzero for rows to compute, or null (rows left unwritten)
 };
 
 // C = alpha A^H B over row blocks: A rows [a_off, a_off + a_cnt) of a
