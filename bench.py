@@ -37,7 +37,39 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); unpacked issue caps at
 PEAK_HBM_GBS = 8000.0
 
 
-def algorithmic_work(cfg, miller_by_k, nbnd):
+# HBM bytes per launch of the H|psi> kernel from rocprofv3 counter runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the same
+# counters read for a 1 GiB device-to-device copy (FETCH x 2.0, WRITE x 1.0),
+# keyed by workload, precision and launch shape, and valid only for the kernel
+# sources they were taken on (hash of the files below).
+KERNEL_SOURCES = ("hpsi_kernel.hpp", "fft.hpp", "internal.hpp")
+MEASURED_TRAFFIC = {
+    ("fcc1-ecut30-fft24-512k", "fp64", (1, 256, 10)): {
+        "sources": "f5fbe76eb4614bef", "fetch_kib": 36153.6, "write_kib": 51200.0,
+        "fetch_scale": 2.0, "write_scale": 1.0,
+        "profile": "profiles/hpsi_fp64_fcc1-ecut30-fft24-512k.md"},
+}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2412_01695_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, prec, shape):
+    """Counter-measured HBM bytes per launch, or None when no counters were
+    taken for this kernel source, workload and shape."""
+    m = MEASURED_TRAFFIC.get((workload, prec, (shape["variant"], shape["threads"], shape["slab"])))
+    if not m or m["sources"] != kernel_source_hash():
+        return None
+    return m["fetch_kib"] * 1024 * m["fetch_scale"] + m["write_kib"] * 1024 * m["write_scale"]
+
+
+def algorithmic_work(cfg, miller_by_k, nbnd, cbytes=16):
     """Flops and I/O bytes per k-band of one H|psi>, averaged over the batch.
 
     Pruned FFT pair with 5 N log2 N flops per complex 1D transform of length
@@ -45,8 +77,9 @@ def algorithmic_work(cfg, miller_by_k, nbnd):
     N3 planes, x on all N2 N3 lines, each both ways; 2 flops per mesh point
     for V(r) u(r); 4 per plane wave for the kinetic term; 8 npw nproj for each
     of lambda = beta^H psi and beta gamma plus 8 nproj^2 for gamma = D lambda.
-    I/O bytes: psi in and H psi out (16 B per complex128 coefficient) plus
-    the projector row block and per-k maps shared by the k's bands."""
+    I/O bytes: psi in and H psi out (cbytes per coefficient: 16 for
+    complex128, 8 for complex64) plus the projector row block and the per-k
+    maps (16 B per plane wave) shared by the k's bands."""
     n1, n2, n3 = cfg.fft
     f1 = lambda n: 5.0 * n * math.log2(n)
     flops = 0.0
@@ -57,7 +90,7 @@ def algorithmic_work(cfg, miller_by_k, nbnd):
         w1 = int(m[:, 0].max() - m[:, 0].min() + 1)
         fft = 2 * (s * f1(n3) + w1 * n3 * f1(n2) + n2 * n3 * f1(n1))
         flops += fft + 2.0 * n1 * n2 * n3 + 4.0 * npw + 16.0 * npw * cfg.nproj + 8.0 * cfg.nproj ** 2
-        io += 2 * 16.0 * npw + (16.0 * cfg.nproj * npw + 16.0 * npw) / nbnd
+        io += 2.0 * cbytes * npw + (cbytes * cfg.nproj * npw + 16.0 * npw) / nbnd
     k = len(miller_by_k)
     return flops / k, io / k
 
@@ -248,7 +281,8 @@ def main():
     psi32 = psi64.to(torch.complex64)
     h32 = torch.empty_like(psi32)
     nkb = cfg.nk * nbnd
-    flops_kb, io_kb = algorithmic_work(cfg, sysm.miller, nbnd)
+    flops_kb, io64_kb = algorithmic_work(cfg, sysm.miller, nbnd)
+    io32_kb = algorithmic_work(cfg, sysm.miller, nbnd, 8)[1]
 
     if args.tune_log:
         mkpw.pw_set_option(sysm.ctx, "tune_log", 1)
@@ -280,6 +314,7 @@ def main():
 
     key = "fp64" if "fp64" in out else "mixed"
     ms = out[key]
+    io_kb = io64_kb if key == "fp64" else io32_kb
     value = nkb / (ms * 1e-3)
     flops_launch = flops_kb * nkb
     achieved_tf = flops_launch / (ms * 1e-3) / 1e12
@@ -305,10 +340,12 @@ def main():
                      "peak": PEAK_FP64_TFLOPS if key == "fp64" else PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s",
                      "frac": achieved_tf / (PEAK_FP64_TFLOPS if key == "fp64" else PEAK_FP32_TFLOPS),
-                     "traffic": None,
+                     "traffic": measured_traffic(cfg.name, key, shapes[key]),
+                     "traffic_unit": "HBM bytes per launch (counters; null if not taken on this kernel)",
                      "kernel": "hpsi_kernel", "shape": shapes[key], "flops_per_kband": flops_kb,
-                     "io_bytes_per_kband": io_kb,
-                     "hbm_io_GBs": io_kb * nkb / (ms * 1e-3) / 1e9},
+                     "io_bytes_per_launch": io_kb * nkb,
+                     "hbm_io_GBs": io_kb * nkb / (ms * 1e-3) / 1e9,
+                     "hbm_frac": io_kb * nkb / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
     }
     if "mixed" in out and "fp64" in out:
         res["mixed"] = {"value": nkb / (out["mixed"] * 1e-3), "ms_per_step": out["mixed"], "dtype": "c64",
