@@ -1,0 +1,409 @@
+// Batched small dense Hermitian kernels for the Rayleigh-Ritz step of the
+// Davidson solver (Sec. 2.1, diagonalisation of the reduced N_base x N_base
+// problem; Sec. 5.2 does it for many k-points at once on the GPU).
+//
+// heevx: the lowest nev eigenpairs of an n x n Hermitian matrix (n <= 64),
+// one workgroup per k-point, everything in LDS:
+//   1. Householder reduction to a Hermitian tridiagonal matrix,
+//      Q^H A Q = T with Q = H_0 H_1 ... H_{n-3}, H_j = I - g_j u_j u_j^H
+//      (Hermitian and unitary, g_j = 2 / |u_j|^2), each applied as the
+//      rank-2 update A <- A - u w^H - w u^H with p = g A u,
+//      w = p - (g/2)(u^H p) u; the u_j stay below the diagonal;
+//   2. a diagonal phase change D (d_0 = 1, d_{j+1} = d_j e_j / |e_j|) making
+//      T = D T_r D^H with T_r real symmetric, off-diagonal |e_j|;
+//   3. eigenvalues of T_r by bisection on Sturm counts (one lane each);
+//   4. eigenvectors of T_r by inverse iteration, Gaussian elimination with
+//      partial pivoting on T_r - lambda (one lane each, from a fixed
+//      pseudo-random start), then Gram-Schmidt (twice) within each cluster of
+//      eigenvalues closer than 1e-3 of the matrix norm;
+//   5. back through D and the reflectors: x = H_0 (... H_{n-3} (D y)).
+// About (4/3) n^3 complex multiply-adds, against roughly 30 n^3 for the cyclic
+// Jacobi sweeps this replaces.
+//
+// chol_inv: Cholesky S = L L^H of a small Hermitian positive-definite overlap
+// and M = L^-H, used to orthonormalise a block of new basis vectors.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace mkpw {
+
+using cd = cplx<double>;
+
+constexpr int kEigMax = 64;   // largest reduced problem
+constexpr int kEigLd = kEigMax + 1;
+constexpr int kEigNev = 32;   // most eigenpairs returned
+
+__device__ __forceinline__ double wave_sum64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+struct EigLds {
+  cd A[kEigMax * kEigLd];                  // matrix, then the reflectors below the diagonal
+  double Y[kEigNev * kEigMax];             // eigenvectors of T_r, one row per eigenpair
+  union {
+    double U[3 * kEigNev * kEigMax];       // per-lane elimination rows (u0, u1, u2)
+    cd Z[kEigNev * kEigLd];                // eigenvectors of A being back-transformed
+  };
+  cd ecx[kEigMax];                         // complex subdiagonal of T
+  cd ph[kEigMax];                          // phases D
+  cd pw[kEigMax];                          // p, then w of the current reflector
+  double g[kEigMax];                       // reflector factors g_j
+  double d[kEigMax], e[kEigMax];           // T_r
+  double lam[kEigNev];
+  int cstart[kEigNev];                     // first index of each eigenvalue's cluster
+  double scal[4];
+};
+
+__global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, long a_kstride, int lda,
+                                                    const int* __restrict__ nk_arr, int nev_req,
+                                                    double* __restrict__ w, cd* __restrict__ Vg, long v_kstride,
+                                                    int ldv) {
+  const int k = blockIdx.x;
+  const int n = nk_arr[k];
+  if (n <= 0) return;
+  const int nev = min(nev_req, n);
+  extern __shared__ __align__(16) unsigned char smem[];
+  EigLds& S = *reinterpret_cast<EigLds*>(smem);
+  cd* A = S.A;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const cd* Ak = Ag + (long)k * a_kstride;
+  for (int e = tid; e < n * n; e += 256) {
+    const int i = e / n, j = e - (e / n) * n;
+    const cd a = Ak[(long)i * lda + j], b = Ak[(long)j * lda + i];  // exact Hermitian part
+    A[i * kEigLd + j] = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+  }
+  __syncthreads();
+
+  // ---- 1. Householder reduction, column j = 0 .. n-3 (trailing rows j+1 .. n-1)
+  for (int j = 0; j + 2 < n; ++j) {
+    const int m = n - j - 1;  // trailing size, 2 .. 63
+    if (wave == 0) {
+      const int i = j + 1 + lane;
+      cd x = {0.0, 0.0};
+      if (lane < m) x = A[i * kEigLd + j];
+      const double sig = wave_sum64(lane >= 1 && lane < m ? x.x * x.x + x.y * x.y : 0.0);
+      const double ar = __shfl(x.x, 0, 64), ai = __shfl(x.y, 0, 64);
+      double gj = 0.0;
+      cd beta = {ar, ai};
+      if (sig > 0.0) {
+        const double amag = sqrt(ar * ar + ai * ai);
+        const double xn = sqrt(amag * amag + sig);
+        // beta = -e^{i arg(alpha)} |x|  (no cancellation in alpha - beta)
+        beta = amag > 0.0 ? cd{-xn * ar / amag, -xn * ai / amag} : cd{-xn, 0.0};
+        const cd u0 = {ar - beta.x, ai - beta.y};
+        gj = 2.0 / (u0.x * u0.x + u0.y * u0.y + sig);
+        if (lane == 0) A[i * kEigLd + j] = u0;
+      }
+      if (lane == 0) {
+        S.g[j] = gj;
+        S.ecx[j] = beta;
+      }
+    }
+    __syncthreads();
+    const double gj = S.g[j];
+    if (gj == 0.0) continue;  // column already reduced (uniform across the workgroup)
+    // p_i = g sum_l A[i][l] u_l, four work-items per row
+    {
+      const int r = tid >> 2, q = tid & 3;
+      cd acc = {0.0, 0.0};
+      if (r < m) {
+        const int i = j + 1 + r;
+        for (int l = q; l < m; l += 4) {
+          const cd a = A[i * kEigLd + j + 1 + l], u = A[(j + 1 + l) * kEigLd + j];
+          acc.x += a.x * u.x - a.y * u.y;
+          acc.y += a.x * u.y + a.y * u.x;
+        }
+      }
+      acc.x += __shfl_xor(acc.x, 1, 64);
+      acc.y += __shfl_xor(acc.y, 1, 64);
+      acc.x += __shfl_xor(acc.x, 2, 64);
+      acc.y += __shfl_xor(acc.y, 2, 64);
+      if (r < m && q == 0) S.pw[r] = {gj * acc.x, gj * acc.y};
+    }
+    __syncthreads();
+    // w = p - (g/2)(u^H p) u
+    if (wave == 0) {
+      cd p = {0.0, 0.0}, u = {0.0, 0.0};
+      if (lane < m) {
+        p = S.pw[lane];
+        u = A[(j + 1 + lane) * kEigLd + j];
+      }
+      const double kk = 0.5 * gj * wave_sum64(u.x * p.x + u.y * p.y);  // Re(u^H p)
+      if (lane < m) S.pw[lane] = {p.x - kk * u.x, p.y - kk * u.y};
+    }
+    __syncthreads();
+    // A <- A - u w^H - w u^H on the trailing block
+    for (int e = tid; e < m * m; e += 256) {
+      const int r = e / m, l = e - (e / m) * m;
+      const cd ur = A[(j + 1 + r) * kEigLd + j], ul = A[(j + 1 + l) * kEigLd + j];
+      const cd wr = S.pw[r], wl = S.pw[l];
+      cd& a = A[(j + 1 + r) * kEigLd + j + 1 + l];
+      // u_r conj(w_l) + w_r conj(u_l)
+      a.x -= ur.x * wl.x + ur.y * wl.y + wr.x * ul.x + wr.y * ul.y;
+      a.y -= ur.y * wl.x - ur.x * wl.y + wr.y * ul.x - wr.x * ul.y;
+    }
+    __syncthreads();
+  }
+
+  // ---- 2. T_r and the phases
+  if (tid == 0) {
+    if (n >= 2) S.ecx[n - 2] = A[(n - 1) * kEigLd + n - 2];  // last subdiagonal, no reflector
+    cd ph = {1.0, 0.0};
+    S.ph[0] = ph;
+    for (int i = 0; i < n; ++i) {
+      S.d[i] = A[i * kEigLd + i].x;
+      if (i + 1 < n) {
+        const cd ei = S.ecx[i];
+        const double mag = sqrt(ei.x * ei.x + ei.y * ei.y);
+        S.e[i] = mag;
+        if (mag > 0.0) ph = {(ph.x * ei.x - ph.y * ei.y) / mag, (ph.x * ei.y + ph.y * ei.x) / mag};
+        S.ph[i + 1] = ph;
+      }
+    }
+    double lo = 1e300, hi = -1e300, nrm = 0.0, emax2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? S.e[i - 1] : 0.0) + (i + 1 < n ? S.e[i] : 0.0);
+      lo = fmin(lo, S.d[i] - r);
+      hi = fmax(hi, S.d[i] + r);
+      nrm = fmax(nrm, fabs(S.d[i]) + r);
+      if (i + 1 < n) emax2 = fmax(emax2, S.e[i] * S.e[i]);
+    }
+    S.scal[0] = lo - 1e-14 * nrm - 1e-300;
+    S.scal[1] = hi + 1e-14 * nrm + 1e-300;
+    S.scal[2] = nrm;
+    S.scal[3] = 2.3e-308 * fmax(1.0, emax2);  // smallest pivot allowed in the Sturm recurrence
+  }
+  __syncthreads();
+
+  // ---- 3.-4. eigenvalues and eigenvectors of T_r, one lane per eigenpair (wave 0)
+  if (wave == 0) {
+    const double nrm = S.scal[2], pivmin = S.scal[3];
+    const int t = lane;
+    if (t < nev) {
+      // bisection: count(x) = number of eigenvalues below x
+      double lo = S.scal[0], hi = S.scal[1];
+      for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(hi - lo > 4.5e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) || mid == lo || mid == hi) break;
+        int cnt = 0;
+        double q = S.d[0] - mid;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+        for (int i = 1; i < n; ++i) {
+          q = (S.d[i] - mid) - S.e[i - 1] * S.e[i - 1] / q;
+          if (fabs(q) < pivmin) q = -pivmin;
+          cnt += q < 0.0;
+        }
+        if (cnt > t) hi = mid;
+        else lo = mid;
+      }
+      const double lm = 0.5 * (lo + hi);
+      S.lam[t] = lm;
+      // inverse iteration on T_r - lm, rows kept in U[(3 t + c) * kEigMax + i]
+      double* y = S.Y + t * kEigMax;
+      double* u0 = S.U + (3 * t + 0) * kEigMax;
+      double* u1 = S.U + (3 * t + 1) * kEigMax;
+      double* u2 = S.U + (3 * t + 2) * kEigMax;
+      const double tiny = 2.2e-16 * fmax(nrm, 1e-300);
+      unsigned h = 0x9E3779B9u * (unsigned)(t + 1);
+      for (int i = 0; i < n; ++i) {  // fixed pseudo-random start in [-1, 1)
+        h ^= h << 13;
+        h ^= h >> 17;
+        h ^= h << 5;
+        y[i] = (double)(h & 0xFFFFFF) / 8388608.0 - 1.0;
+      }
+      for (int iter = 0; iter < 3; ++iter) {
+        // forward elimination with partial pivoting, right-hand side y
+        double c0 = S.d[0] - lm, c1 = n > 1 ? S.e[0] : 0.0, rc = y[0];
+        for (int i = 0; i + 1 < n; ++i) {
+          const double s = S.e[i], dd = S.d[i + 1] - lm, ee = i + 2 < n ? S.e[i + 1] : 0.0, b1 = y[i + 1];
+          if (fabs(c0) >= fabs(s)) {
+            const double l = c0 != 0.0 ? s / c0 : 0.0;
+            u0[i] = c0;
+            u1[i] = c1;
+            u2[i] = 0.0;
+            y[i] = rc;
+            c0 = dd - l * c1;
+            c1 = ee;
+            rc = b1 - l * rc;
+          } else {
+            const double l = c0 / s;
+            u0[i] = s;
+            u1[i] = dd;
+            u2[i] = ee;
+            y[i] = b1;
+            const double n0 = c1 - l * dd;
+            c1 = -l * ee;
+            c0 = n0;
+            rc = rc - l * b1;
+          }
+        }
+        u0[n - 1] = c0;
+        y[n - 1] = rc;
+        // back substitution (tiny pivots replaced by eps |T|), then normalise
+        double y1 = 0.0, y2 = 0.0, ss = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+          double piv = u0[i];
+          if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
+          const double v = (y[i] - (i + 1 < n ? u1[i] * y1 : 0.0) - (i + 2 < n ? u2[i] * y2 : 0.0)) / piv;
+          y[i] = v;
+          y2 = y1;
+          y1 = v;
+          ss = fmax(ss, fabs(v));
+        }
+        const double sc = ss > 0.0 ? 1.0 / ss : 1.0;
+        for (int i = 0; i < n; ++i) y[i] *= sc;
+      }
+    }
+  }
+  __syncthreads();
+  // clusters of close eigenvalues (ascending)
+  if (tid == 0) {
+    int cs = 0;
+    for (int i = 0; i < nev; ++i) {
+      if (i > 0 && S.lam[i] - S.lam[i - 1] > 1e-3 * S.scal[2]) cs = i;
+      S.cstart[i] = cs;
+    }
+  }
+  __syncthreads();
+  // Gram-Schmidt (twice) within each cluster, in ascending order; lane i owns
+  // component i of every vector, so only the wave sums cross lanes
+  if (wave == 0) {
+    for (int t2 = 0; t2 < nev; ++t2) {
+      double* yt = S.Y + t2 * kEigMax;
+      double v = lane < n ? yt[lane] : 0.0;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int s2 = S.cstart[t2]; s2 < t2; ++s2) {
+          const double ys = lane < n ? S.Y[s2 * kEigMax + lane] : 0.0;
+          v -= wave_sum64(ys * v) * ys;
+        }
+        const double nn = wave_sum64(v * v);
+        v *= nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+      }
+      if (lane < n) yt[lane] = v;
+    }
+  }
+  __syncthreads();
+
+  // ---- 5. x = H_0 (... H_{n-3} (D y)): wave v takes eigenpairs v, v + 4, ...,
+  //         lane i holds component i
+  for (int t = wave; t < nev; t += 4) {
+    cd* z = S.Z + t * kEigLd;
+    const double yv = lane < n ? S.Y[t * kEigMax + lane] : 0.0;
+    cd zi = {0.0, 0.0};
+    if (lane < n) zi = {S.ph[lane].x * yv, S.ph[lane].y * yv};
+    for (int j = n - 3; j >= 0; --j) {
+      const double gj = S.g[j];
+      if (gj == 0.0) continue;
+      cd u = {0.0, 0.0};
+      if (lane > j && lane < n) u = A[lane * kEigLd + j];
+      // c = g u^H z
+      const double cr = gj * wave_sum64(u.x * zi.x + u.y * zi.y);
+      const double ci = gj * wave_sum64(u.x * zi.y - u.y * zi.x);
+      zi.x -= cr * u.x - ci * u.y;
+      zi.y -= cr * u.y + ci * u.x;
+    }
+    if (lane < n) z[lane] = zi;
+  }
+  __syncthreads();
+  if (tid < nev) w[(long)k * nev_req + tid] = S.lam[tid];
+  cd* Vk = Vg + (long)k * v_kstride;
+  for (int e = tid; e < n * nev; e += 256) {
+    const int r = e / nev, t = e - (e / nev) * nev;
+    Vk[(long)r * ldv + t] = S.Z[t * kEigLd + r];
+  }
+}
+
+constexpr int kCholMax = 32;
+
+__global__ __launch_bounds__(64) void chol_inv_kernel(const cd* __restrict__ Sg, long s_kstride, int lds,
+                                                      const int* __restrict__ nk_arr, cd* __restrict__ Mg,
+                                                      long m_kstride, int ldm, int* __restrict__ info) {
+  const int k = blockIdx.x;
+  const int n = nk_arr[k];
+  if (n <= 0) {
+    if (threadIdx.x == 0) info[k] = 0;
+    return;
+  }
+  __shared__ cd L[kCholMax][kCholMax + 1];
+  __shared__ cd Li[kCholMax][kCholMax + 1];
+  __shared__ int bad;
+  __shared__ double dmax;
+  const int tid = threadIdx.x;
+  const cd* S = Sg + (long)k * s_kstride;
+  for (int e = tid; e < n * n; e += 64) L[e / n][e % n] = S[(long)(e / n) * lds + (e % n)];
+  if (tid == 0) {
+    bad = 0;
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, L[i][i].x);
+    dmax = m;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      double d = L[j][j].x;
+      for (int q = 0; q < j; ++q) d -= L[j][q].x * L[j][q].x + L[j][q].y * L[j][q].y;
+      if (!(d > 1e-12 * dmax)) bad = 1;
+      L[j][j] = {sqrt(fmax(d, 1e-300)), 0.0};
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < n; i += 64) {
+      double xr = L[i][j].x, xi = L[i][j].y;
+      for (int q = 0; q < j; ++q) {  // - L[i][q] conj(L[j][q])
+        cd a = L[i][q], b = L[j][q];
+        xr -= a.x * b.x + a.y * b.y;
+        xi -= a.y * b.x - a.x * b.y;
+      }
+      double inv = 1.0 / L[j][j].x;
+      L[i][j] = {xr * inv, xi * inv};
+    }
+    __syncthreads();
+  }
+  // columns of L^-1 by forward substitution, one column per work-item
+  for (int c = tid; c < n; c += 64) {
+    for (int i = 0; i < n; ++i) Li[i][c] = {0.0, 0.0};
+    for (int i = c; i < n; ++i) {
+      double xr = (i == c) ? 1.0 : 0.0, xi = 0.0;
+      for (int q = c; q < i; ++q) {
+        cd a = L[i][q], b = Li[q][c];
+        xr -= a.x * b.x - a.y * b.y;
+        xi -= a.x * b.y + a.y * b.x;
+      }
+      double inv = 1.0 / L[i][i].x;
+      Li[i][c] = {xr * inv, xi * inv};
+    }
+  }
+  __syncthreads();
+  cd* M = Mg + (long)k * m_kstride;
+  for (int e = tid; e < n * n; e += 64) {
+    int i = e / n, j = e % n;  // M = Li^H (upper triangular)
+    cd v = Li[j][i];
+    M[(long)i * ldm + j] = {v.x, -v.y};
+  }
+  if (tid == 0) info[k] = bad;
+}
+
+pw_status launch_heev(pw_ctx* c, const cd* A, long a_kstride, int lda, const int* n, int nmax, int nev, double* w,
+                      cd* V, long v_kstride, int ldv, hipStream_t st) {
+  if (nmax > kEigMax) return set_err(c, PW_EINVAL, "reduced problem larger than 64");
+  if (nev > kEigNev) return set_err(c, PW_EINVAL, "more than 32 eigenpairs requested");
+  const size_t lds = sizeof(EigLds);
+  {
+    pw_status s = ensure_lds_limit(c, (const void*)heevx_kernel, lds);
+    if (s != PW_OK) return s;
+  }
+  hipLaunchKernelGGL(heevx_kernel, dim3(c->nk), dim3(256), lds, st, A, a_kstride, lda, n, nev, w, V, v_kstride, ldv);
+  return check_launch(c, "heevx", st);
+}
+
+pw_status launch_chol_inv(pw_ctx* c, const cd* S, long s_kstride, int lds, const int* n, cd* M, long m_kstride,
+                          int ldm, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(c->nk), dim3(64), 0, st, S, s_kstride, lds, n, M, m_kstride, ldm, info);
+  return check_launch(c, "chol_inv", st);
+}
+
+}  // namespace mkpw

@@ -535,6 +535,7 @@ extern std::mutex g_hpsi_tune_mu;
 extern std::map<std::vector<long>, HpsiShape> g_hpsi_tuned;
 
 constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr long kTuneMinRows = 4096;  // smallest launch (in (k, band) rows) that is autotuned
 
 template <class T, int N, int WC>
 size_t hpsi_lds(const KTables& t, int l3c, int nproj, int threads) {
@@ -691,14 +692,39 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
       return set_err(c, PW_EINVAL, "requested H|psi> slab does not fit in LDS");
     return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh);
   }
-  // autotune once per (precision, mesh, window, stick count, row-count bucket)
-  long rows = 1;
+  // autotune once per (precision, mesh, window capacity, row-count bucket);
+  // launches of fewer rows than kTuneMinRows are not worth timing and take the
+  // shape tuned for the smallest bucket seen, else a fixed default
+  long rows = kTuneMinRows;
   while (rows < (long)t.nk * sel.nvec) rows <<= 1;
-  const std::vector<long> key = {(long)sizeof(T), N, WC, t.smax, t.wx, nproj, rows};
+  const std::vector<long> key = {(long)sizeof(T), N, WC, rows};
+  auto fits = [&](HpsiShape& sh) {  // narrow the slab to this context's LDS need
+    while (sh.l3c > 1 && hpsi_lds<T, N, WC>(t, sh.l3c, nproj, sh.threads) > kLdsPerCu) --sh.l3c;
+    return hpsi_lds<T, N, WC>(t, sh.l3c, nproj, sh.threads) <= kLdsPerCu;
+  };
   {
     std::lock_guard<std::mutex> lk(g_hpsi_tune_mu);
     auto it = g_hpsi_tuned.find(key);
-    if (it != g_hpsi_tuned.end()) return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, it->second);
+    if (it == g_hpsi_tuned.end() && (long)t.nk * sel.nvec < kTuneMinRows) {
+      for (auto jt = g_hpsi_tuned.begin(); jt != g_hpsi_tuned.end(); ++jt)
+        if (jt->first[0] == (long)sizeof(T) && jt->first[1] == N && jt->first[2] == WC) {
+          it = jt;  // the map orders keys, so this is the smallest bucket
+          break;
+        }
+    }
+    if (it != g_hpsi_tuned.end()) {
+      HpsiShape sh = it->second;
+      if (fits(sh)) return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh);
+    }
+  }
+  if ((long)t.nk * sel.nvec < kTuneMinRows) {
+    HpsiShape sh;
+    sh.variant = (N % 2 == 0 && N >= 30) ? 2 : 1;
+    sh.threads = sh.variant == 2 ? 512 : 256;
+    sh.l3c = std::min(N, std::max(1, sh.threads / ((sh.variant == 2 ? 2 : 1) * N)));
+    while (sh.l3c > 1 && hpsi_lds<T, N, WC>(t, sh.l3c, nproj, sh.threads) > kLdsPerCu / 2) --sh.l3c;
+    if (!fits(sh)) return set_err(c, PW_EINVAL, "H|psi> working set does not fit in LDS for this mesh");
+    return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh);
   }
   auto cands = hpsi_candidates<T, N, WC>(t, nproj);
   if (cands.empty()) return set_err(c, PW_EINVAL, "H|psi> working set does not fit in LDS for this mesh");

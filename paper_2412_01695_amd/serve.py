@@ -86,6 +86,7 @@ class Request:
         self.iters = None
         self.status = None
         self.error = None
+        self.t_setup = self.t_solve = None   # host set-up (basis, maps, potential, projectors), device solve
         npwx = (npw_estimate(cfg) + 63) // 64 * 64
         self.bytes = footprint_bytes(cfg.nk, npwx, cfg.nbnd, cfg.nproj, prec)
 
@@ -167,6 +168,7 @@ class Server:
     def _solve(self, r, stream):
         torch = self.torch
         cfg = r.cfg
+        t0 = time.monotonic()
         ctx = mkpw.pw_create(self.device, stream.cuda_stream)
         try:
             mkpw.pw_set_lattice(ctx, cfg.lat)
@@ -182,11 +184,13 @@ class Server:
             beta[kidx, gidx, :] = synth.beta_values(cfg, q).T
             beta = np.ascontiguousarray(beta.transpose(0, 2, 1))
             mkpw.pw_set_projectors(ctx, beta, cfg.dij)
+            t1 = time.monotonic()
             with torch.cuda.stream(stream):
                 d_psi = torch.empty((cfg.nk, cfg.nbnd, npwx), dtype=torch.complex128, device=f"cuda:{self.device}")
                 mkpw.pw_init_guess(ctx, cfg.nbnd, cfg.seed, d_psi)
                 st, eig, iters, conv = mkpw.pw_davidson(ctx, r.prec, cfg.nbnd, d_psi, cfg.nk, r.tol_ry, r.max_iter)
                 stream.synchronize()
+            r.t_setup, r.t_solve = t1 - t0, time.monotonic() - t1
             r.status, r.eig, r.iters = st, eig, iters
             self._keep(r.id, eig, d_psi)
         finally:
@@ -232,9 +236,15 @@ def replay(reqs, server: Server, speed=1.0):
 
 
 def summarize(reqs, wall):
-    lat = np.array([r.latency for r in reqs if r.status == 0])
-    kb = sum(r.cfg.nk * r.cfg.nbnd for r in reqs if r.status == 0)
+    ok = [r for r in reqs if r.status == 0]
+    lat = np.array([r.latency for r in ok])
+    kb = sum(r.cfg.nk * r.cfg.nbnd for r in ok)
+
+    def mean(v):
+        return float(np.mean(v)) if len(v) else None
     return {"requests": len(reqs), "ok": int(lat.size),
+            "mean_queue_s": mean([r.admitted - r.arrival for r in ok]),
+            "mean_setup_s": mean([r.t_setup for r in ok]), "mean_solve_s": mean([r.t_solve for r in ok]),
             "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_s": float(lat.mean()) if lat.size else None,
