@@ -42,7 +42,7 @@ PEAK_HBM_GBS = 8000.0
 # counters read for a 1 GiB device-to-device copy (FETCH x 2.0, WRITE x 1.0),
 # keyed by workload, precision and launch shape, and valid only for the kernel
 # sources they were taken on (hash of the files below).
-KERNEL_SOURCES = ("hpsi_kernel.hpp", "fft.hpp", "internal.hpp")
+KERNEL_SOURCES = ("hpsi_kernel.hpp", "fft.hpp", "internal.hpp", "wave.hpp")
 MEASURED_TRAFFIC = {
     ("fcc1-ecut30-fft24-512k", "fp64", (1, 256, 10)): {
         "sources": "f5fbe76eb4614bef", "fetch_kib": 36153.6, "write_kib": 51200.0,

@@ -27,6 +27,7 @@
 #include <cmath>
 
 #include "internal.hpp"
+#include "wave.hpp"
 
 namespace mkpw {
 
@@ -36,9 +37,26 @@ constexpr int kEigMax = 64;   // largest reduced problem
 constexpr int kEigLd = kEigMax + 1;
 constexpr int kEigNev = 32;   // most eigenpairs returned
 
-__device__ __forceinline__ double wave_sum64(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+__device__ __forceinline__ double wave_sum64(double v) { return wave_sum(v); }
+
+// Householder reflector of a column held one component per lane (x on lane
+// l < mm, zero beyond): H = I - g u u^H with H x = beta e_0, beta = -e^{i arg
+// x_0} |x|, u = x - beta e_0; g = 0 (no reflection, beta = x_0) when x has
+// nothing below its first component.  Called by a whole wave.
+__device__ __forceinline__ void make_reflector(cd x, int mm, int lane, double& g, cd& beta, cd& u) {
+  const double sig = wave_sum64(lane >= 1 && lane < mm ? x.x * x.x + x.y * x.y : 0.0);
+  const double ar = __shfl(x.x, 0, 64), ai = __shfl(x.y, 0, 64);
+  g = 0.0;
+  beta = {ar, ai};
+  u = x;
+  if (sig > 0.0) {
+    const double amag = sqrt(ar * ar + ai * ai);
+    const double xn = sqrt(amag * amag + sig);
+    beta = amag > 0.0 ? cd{-xn * ar / amag, -xn * ai / amag} : cd{-xn, 0.0};
+    const cd u0 = {ar - beta.x, ai - beta.y};
+    g = 2.0 / (u0.x * u0.x + u0.y * u0.y + sig);
+    if (lane == 0) u = u0;
+  }
 }
 
 struct EigLds {
@@ -78,36 +96,28 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
   }
   __syncthreads();
 
-  // ---- 1. Householder reduction, column j = 0 .. n-3 (trailing rows j+1 .. n-1)
+  // ---- 1. Householder reduction, column j = 0 .. n-3 (trailing rows j+1 .. n-1).
+  //         Two barriers per column: p = g A u over the trailing block, then the
+  //         rank-2 update, during which wave 0 also updates column j+1 and
+  //         forms its reflector from the new values held in registers.
+  if (wave == 0 && n >= 3) {
+    cd x = {0.0, 0.0};
+    if (lane < n - 1) x = A[(1 + lane) * kEigLd];
+    double g0;
+    cd beta, u;
+    make_reflector(x, n - 1, lane, g0, beta, u);
+    if (lane < n - 1) A[(1 + lane) * kEigLd] = u;
+    if (lane == 0) {
+      S.g[0] = g0;
+      S.ecx[0] = beta;
+    }
+  }
+  __syncthreads();
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;  // trailing size, 2 .. 63
-    if (wave == 0) {
-      const int i = j + 1 + lane;
-      cd x = {0.0, 0.0};
-      if (lane < m) x = A[i * kEigLd + j];
-      const double sig = wave_sum64(lane >= 1 && lane < m ? x.x * x.x + x.y * x.y : 0.0);
-      const double ar = __shfl(x.x, 0, 64), ai = __shfl(x.y, 0, 64);
-      double gj = 0.0;
-      cd beta = {ar, ai};
-      if (sig > 0.0) {
-        const double amag = sqrt(ar * ar + ai * ai);
-        const double xn = sqrt(amag * amag + sig);
-        // beta = -e^{i arg(alpha)} |x|  (no cancellation in alpha - beta)
-        beta = amag > 0.0 ? cd{-xn * ar / amag, -xn * ai / amag} : cd{-xn, 0.0};
-        const cd u0 = {ar - beta.x, ai - beta.y};
-        gj = 2.0 / (u0.x * u0.x + u0.y * u0.y + sig);
-        if (lane == 0) A[i * kEigLd + j] = u0;
-      }
-      if (lane == 0) {
-        S.g[j] = gj;
-        S.ecx[j] = beta;
-      }
-    }
-    __syncthreads();
-    const double gj = S.g[j];
-    if (gj == 0.0) continue;  // column already reduced (uniform across the workgroup)
-    // p_i = g sum_l A[i][l] u_l, four work-items per row
-    {
+    const double gj = S.g[j];  // uniform
+    if (gj != 0.0) {
+      // p_r = g sum_l A[j+1+r][j+1+l] u_l, four work-items per row
       const int r = tid >> 2, q = tid & 3;
       cd acc = {0.0, 0.0};
       if (r < m) {
@@ -125,26 +135,58 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
       if (r < m && q == 0) S.pw[r] = {gj * acc.x, gj * acc.y};
     }
     __syncthreads();
-    // w = p - (g/2)(u^H p) u
-    if (wave == 0) {
+    // w = p - K u with K = (g/2) Re(u^H p), formed by every wave for itself
+    double kk = 0.0;
+    if (gj != 0.0) {
       cd p = {0.0, 0.0}, u = {0.0, 0.0};
       if (lane < m) {
         p = S.pw[lane];
         u = A[(j + 1 + lane) * kEigLd + j];
       }
-      const double kk = 0.5 * gj * wave_sum64(u.x * p.x + u.y * p.y);  // Re(u^H p)
-      if (lane < m) S.pw[lane] = {p.x - kk * u.x, p.y - kk * u.y};
+      kk = 0.5 * gj * wave_sum64(u.x * p.x + u.y * p.y);
     }
-    __syncthreads();
-    // A <- A - u w^H - w u^H on the trailing block
-    for (int e = tid; e < m * m; e += 256) {
-      const int r = e / m, l = e - (e / m) * m;
-      const cd ur = A[(j + 1 + r) * kEigLd + j], ul = A[(j + 1 + l) * kEigLd + j];
-      const cd wr = S.pw[r], wl = S.pw[l];
-      cd& a = A[(j + 1 + r) * kEigLd + j + 1 + l];
-      // u_r conj(w_l) + w_r conj(u_l)
-      a.x -= ur.x * wl.x + ur.y * wl.y + wr.x * ul.x + wr.y * ul.y;
-      a.y -= ur.y * wl.x - ur.x * wl.y + wr.y * ul.x - wr.x * ul.y;
+    if (wave == 0) {
+      // column j+1 of the trailing block (row j+1+lane), updated in registers
+      cd a = {0.0, 0.0};
+      if (lane < m) a = A[(j + 1 + lane) * kEigLd + j + 1];
+      if (gj != 0.0 && lane < m) {
+        const cd ur = A[(j + 1 + lane) * kEigLd + j], u0 = A[(j + 1) * kEigLd + j];
+        const cd pr = S.pw[lane], p0 = S.pw[0];
+        const cd wr = {pr.x - kk * ur.x, pr.y - kk * ur.y}, w0 = {p0.x - kk * u0.x, p0.y - kk * u0.y};
+        // a -= u_r conj(w_0) + w_r conj(u_0)
+        a.x -= ur.x * w0.x + ur.y * w0.y + wr.x * u0.x + wr.y * u0.y;
+        a.y -= ur.y * w0.x - ur.x * w0.y + wr.y * u0.x - wr.x * u0.y;
+      }
+      cd st = a;  // value stored at row j+1+lane of column j+1
+      if (j + 3 < n) {
+        // reflector of column j+1 from rows j+2 .. n-1: component lane+1 on lane
+        cd x = {__shfl(a.x, lane + 1 < 64 ? lane + 1 : 63, 64), __shfl(a.y, lane + 1 < 64 ? lane + 1 : 63, 64)};
+        if (lane >= m - 1) x = {0.0, 0.0};
+        double g1;
+        cd beta, u;
+        make_reflector(x, m - 1, lane, g1, beta, u);
+        const cd ub = {__shfl(u.x, lane > 0 ? lane - 1 : 0, 64), __shfl(u.y, lane > 0 ? lane - 1 : 0, 64)};
+        if (lane >= 1) st = ub;
+        if (lane == 0) {
+          S.g[j + 1] = g1;
+          S.ecx[j + 1] = beta;
+        }
+      }
+      if (lane < m) A[(j + 1 + lane) * kEigLd + j + 1] = st;
+    }
+    if (gj != 0.0) {
+      // the rest of the trailing block (columns j+2 ..): A -= u w^H + w u^H
+      const int mc = m - 1;
+      for (int e = tid; e < m * mc; e += 256) {
+        const int r = e / mc, l = 1 + e - (e / mc) * mc;
+        const cd ur = A[(j + 1 + r) * kEigLd + j], ul = A[(j + 1 + l) * kEigLd + j];
+        const cd pr = S.pw[r], pl = S.pw[l];
+        const cd wr = {pr.x - kk * ur.x, pr.y - kk * ur.y}, wl = {pl.x - kk * ul.x, pl.y - kk * ul.y};
+        cd& av = A[(j + 1 + r) * kEigLd + j + 1 + l];
+        // u_r conj(w_l) + w_r conj(u_l)
+        av.x -= ur.x * wl.x + ur.y * wl.y + wr.x * ul.x + wr.y * ul.y;
+        av.y -= ur.y * wl.x - ur.x * wl.y + wr.y * ul.x - wr.x * ul.y;
+      }
     }
     __syncthreads();
   }
@@ -179,30 +221,46 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
   }
   __syncthreads();
 
-  // ---- 3.-4. eigenvalues and eigenvectors of T_r, one lane per eigenpair (wave 0)
-  if (wave == 0) {
-    const double nrm = S.scal[2], pivmin = S.scal[3];
-    const int t = lane;
-    if (t < nev) {
-      // bisection: count(x) = number of eigenvalues below x
+  // ---- 3. eigenvalues of T_r: four work-items per eigenvalue; each step
+  //         counts the eigenvalues below four interior points of the bracket
+  //         (Sturm sequence) and keeps the fifth of it that holds eigenvalue t
+  {
+    const int t = tid >> 2, sub = tid & 3;
+    if (t < nev) {  // whole quads
+      const double pivmin = S.scal[3];
       double lo = S.scal[0], hi = S.scal[1];
-      for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (!(hi - lo > 4.5e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) || mid == lo || mid == hi) break;
+      for (int it = 0; it < 100; ++it) {
+        if (!(hi - lo > 4.5e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
+        const double x = lo + (hi - lo) * (0.2 * (sub + 1));
         int cnt = 0;
-        double q = S.d[0] - mid;
+        double q = S.d[0] - x;
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
         for (int i = 1; i < n; ++i) {
-          q = (S.d[i] - mid) - S.e[i - 1] * S.e[i - 1] / q;
+          q = (S.d[i] - x) - S.e[i - 1] * S.e[i - 1] / q;
           if (fabs(q) < pivmin) q = -pivmin;
           cnt += q < 0.0;
         }
-        if (cnt > t) hi = mid;
-        else lo = mid;
+        double lc = cnt <= t ? x : lo, hc = cnt > t ? x : hi;
+        lc = fmax(lc, __shfl_xor(lc, 1, 64));
+        lc = fmax(lc, __shfl_xor(lc, 2, 64));
+        hc = fmin(hc, __shfl_xor(hc, 1, 64));
+        hc = fmin(hc, __shfl_xor(hc, 2, 64));
+        if (lc == lo && hc == hi) break;  // the points no longer split the bracket
+        lo = lc;
+        hi = hc;
       }
-      const double lm = 0.5 * (lo + hi);
-      S.lam[t] = lm;
+      if (sub == 0) S.lam[t] = 0.5 * (lo + hi);
+    }
+  }
+  __syncthreads();
+
+  // ---- 4. eigenvectors of T_r, one lane per eigenpair (wave 0)
+  if (wave == 0) {
+    const double nrm = S.scal[2];
+    const int t = lane;
+    if (t < nev) {
+      const double lm = S.lam[t];
       // inverse iteration on T_r - lm, rows kept in U[(3 t + c) * kEigMax + i]
       double* y = S.Y + t * kEigMax;
       double* u0 = S.U + (3 * t + 0) * kEigMax;
