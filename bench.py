@@ -69,7 +69,7 @@ def measured_traffic(workload, prec, shape):
     return m["fetch_kib"] * 1024 * m["fetch_scale"] + m["write_kib"] * 1024 * m["write_scale"]
 
 
-def algorithmic_work(cfg, miller_by_k, nbnd, cbytes=16):
+def algorithmic_work(cfg, miller_by_k, nbnd, cbytes=16, with_3pass=False):
     """Flops and I/O bytes per k-band of one H|psi>, averaged over the batch.
 
     Pruned FFT pair with 5 N log2 N flops per complex 1D transform of length
@@ -79,19 +79,29 @@ def algorithmic_work(cfg, miller_by_k, nbnd, cbytes=16):
     of lambda = beta^H psi and beta gamma plus 8 nproj^2 for gamma = D lambda.
     I/O bytes: psi in and H psi out (cbytes per coefficient: 16 for
     complex128, 8 for complex64) plus the projector row block and the per-k
-    maps (16 B per plane wave) shared by the k's bands."""
+    maps (16 B per plane wave) shared by the k's bands.  With with_3pass, also
+    the bytes of a three-pass (unfused) FFT that keeps the y-transformed
+    planes in HBM between passes (4 W1 N^2 coefficients more per k-band): the
+    bound such a design could not beat."""
     n1, n2, n3 = cfg.fft
     f1 = lambda n: 5.0 * n * math.log2(n)
     flops = 0.0
     io = 0.0
+    io3 = 0.0
     for m in miller_by_k:
         npw = m.shape[0]
         s = len({(int(a), int(b)) for a, b, _ in m})
         w1 = int(m[:, 0].max() - m[:, 0].min() + 1)
         fft = 2 * (s * f1(n3) + w1 * n3 * f1(n2) + n2 * n3 * f1(n1))
         flops += fft + 2.0 * n1 * n2 * n3 + 4.0 * npw + 16.0 * npw * cfg.nproj + 8.0 * cfg.nproj ** 2
-        io += 2.0 * cbytes * npw + (cbytes * cfg.nproj * npw + 16.0 * npw) / nbnd
+        kio = 2.0 * cbytes * npw + (cbytes * cfg.nproj * npw + 16.0 * npw) / nbnd
+        io += kio
+        # an unfused design keeps the W1 planes of y-transformed data in HBM
+        # between its three passes: written, read and written back, read
+        io3 += kio + 4.0 * w1 * n2 * n3 * cbytes
     k = len(miller_by_k)
+    if with_3pass:
+        return flops / k, io / k, io3 / k
     return flops / k, io / k
 
 
@@ -281,8 +291,8 @@ def main():
     psi32 = psi64.to(torch.complex64)
     h32 = torch.empty_like(psi32)
     nkb = cfg.nk * nbnd
-    flops_kb, io64_kb = algorithmic_work(cfg, sysm.miller, nbnd)
-    io32_kb = algorithmic_work(cfg, sysm.miller, nbnd, 8)[1]
+    flops_kb, io64_kb, io64_3p = algorithmic_work(cfg, sysm.miller, nbnd, 16, True)
+    _, io32_kb, io32_3p = algorithmic_work(cfg, sysm.miller, nbnd, 8, True)
 
     if args.tune_log:
         mkpw.pw_set_option(sysm.ctx, "tune_log", 1)
@@ -315,6 +325,7 @@ def main():
     key = "fp64" if "fp64" in out else "mixed"
     ms = out[key]
     io_kb = io64_kb if key == "fp64" else io32_kb
+    io_3p = io64_3p if key == "fp64" else io32_3p
     value = nkb / (ms * 1e-3)
     flops_launch = flops_kb * nkb
     achieved_tf = flops_launch / (ms * 1e-3) / 1e12
@@ -345,7 +356,9 @@ def main():
                      "kernel": "hpsi_kernel", "shape": shapes[key], "flops_per_kband": flops_kb,
                      "io_bytes_per_launch": io_kb * nkb,
                      "hbm_io_GBs": io_kb * nkb / (ms * 1e-3) / 1e9,
-                     "hbm_frac": io_kb * nkb / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
+                     "hbm_frac": io_kb * nkb / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "hbm_3pass_bound_kband_s": PEAK_HBM_GBS * 1e9 / io_3p,
+                     "vs_hbm_3pass_bound": value / (PEAK_HBM_GBS * 1e9 / io_3p)},
     }
     if "mixed" in out and "fp64" in out:
         res["mixed"] = {"value": nkb / (out["mixed"] * 1e-3), "ms_per_step": out["mixed"], "dtype": "c64",

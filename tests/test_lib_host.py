@@ -111,6 +111,23 @@ def test_error_paths(mk):
     mk.pw_destroy(ctx)
 
 
+def test_shape_options(mk):
+    # the H|psi> launch-shape options: accepted values round-trip, others are refused
+    ctx = mk.pw_create(-1, None)
+    for key, good, bad in (("hpsi_variant", (0, 1, 2), (-1, 3)), ("hpsi_threads", (0, 256, 512, 1024), (128, 300)),
+                           ("hpsi_slab", (0, 1, 36), (-1, 513)), ("tune_log", (0, 1), ())):
+        for v in good:
+            mk.pw_set_option(ctx, key, v)
+            assert mk.pw_get_option(ctx, key) == v
+        for v in bad:
+            with pytest.raises(mk.PwError) as e:
+                mk.pw_set_option(ctx, key, v)
+            assert e.value.status == mk.PW_EINVAL
+    for key in ("hpsi_variant_tuned", "hpsi_slab_tuned", "hpsi_threads_tuned"):
+        assert mk.pw_get_option(ctx, key) == 0  # nothing launched yet
+    mk.pw_destroy(ctx)
+
+
 def test_single_hip_runtime_whatever_the_import_order():
     # the binding must bind the library to torch's HIP runtime even when it is
     # imported before torch; two runtimes in one process crash on first use
