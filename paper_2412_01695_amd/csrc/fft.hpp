@@ -1,11 +1,13 @@
-// In-register mixed-radix (2, 3, 4, 5) complex FFT for one thread.
+// In-register mixed-radix (2, 3, 4, 5) and prime-factor complex FFT for one
+// thread.
 //
 // The 3D transform of the paper (Sec. 4, Eqs. zfft, yfft, xfft, fwFFT) is a
 // sequence of 1D transforms of length N_i along each axis.  Here every 1D
 // line is held by one work-item in registers and transformed with a fully
-// unrolled decimation-in-time Cooley-Tukey recursion whose every index and
-// twiddle factor is a compile-time constant, so the data never leaves the
-// VGPRs and every twiddle is an immediate/SGPR operand.  Lines are exchanged
+// unrolled recursion -- Good-Thomas prime-factor splits where the length has
+// coprime factors, decimation-in-time Cooley-Tukey otherwise -- whose every
+// index and twiddle factor is a compile-time constant, so the data never
+// leaves the VGPRs and every twiddle is an immediate/SGPR operand.  Lines are exchanged
 // between axes through LDS by the calling kernel.
 //
 //   SIGN = +1 : X[l] = sum_m x[m] exp(+2 pi i l m / N)   (inverse, unnormalised)
@@ -190,17 +192,11 @@ __device__ __forceinline__ void bfly(cplx<T> (&a)[R]) {
   }
 }
 
-// First radix of the decimation-in-time split.  Inverse transforms here
-// always start from a window of nonzero inputs and forward ones always end in
-// a window of wanted outputs; for 24, 30 and 36 points a different first
-// split lets the most operations on the zeros (or on the unwanted outputs)
-// fold away in each direction (chosen by counting the generated instructions).
-template <int N, int SIGN>
+// First radix of a Cooley-Tukey (decimation in time) split, for lengths that
+// have no coprime factorisation (powers of 2 and 3) and for the odd primes.
+template <int N>
 constexpr int pick_radix() {
-  if constexpr (N == 24) return SIGN > 0 ? 8 : 3;
-  else if constexpr (N == 30) return SIGN > 0 ? 3 : 5;
-  else if constexpr (N == 36) return 3;
-  else if constexpr (N == 1 || N == 2 || N == 3 || N == 4 || N == 5) return N;
+  if constexpr (N == 1 || N == 2 || N == 3 || N == 4 || N == 5) return N;
   else if constexpr (N % 4 == 0) return 4;
   else if constexpr (N % 2 == 0) return 2;
   else if constexpr (N % 3 == 0) return 3;
@@ -208,11 +204,68 @@ constexpr int pick_radix() {
   else return N;  // prime: direct (odd) butterfly
 }
 
+// First factor N1 of a prime-factor (Good-Thomas) split N = N1 N2 with N1, N2
+// coprime, 0 for none.  Inverse transforms here always start from a window of
+// nonzero inputs and forward ones always end in a window of wanted outputs;
+// the split that lets the most operations on the zeros (or on the unwanted
+// outputs) fold away differs with the direction, and was chosen by counting
+// the generated FP64 instructions (e.g. 24 points: 196 for 10 -> 24 inverse,
+// 228 for 24 -> 10 forward, against 224 and 256 with radix-4 Cooley-Tukey).
+template <int N, int SIGN>
+constexpr int pfa_first() {
+  if constexpr (N == 6 || N == 10 || N == 18) return 2;
+  else if constexpr (N == 12) return 3;
+  else if constexpr (N == 15) return SIGN > 0 ? 5 : 3;
+  else if constexpr (N == 20) return SIGN > 0 ? 5 : 4;
+  else if constexpr (N == 24) return SIGN > 0 ? 8 : 3;
+  else if constexpr (N == 30) return SIGN > 0 ? 15 : 2;
+  else if constexpr (N == 36) return 4;
+  else return 0;
+}
+
+template <int A, int M>
+constexpr int inv_mod() {  // A^-1 mod M for coprime A, M
+  for (int q = 1; q < M; ++q)
+    if ((A * q) % M == 1) return q;
+  return 1;
+}
+
+// Prime-factor DFT: with n = (n1 N2 + n2 N1) mod N on the input and
+// k = (k1 N2 q2 + k2 N1 q1) mod N on the output (q2 = N2^-1 mod N1,
+// q1 = N1^-1 mod N2), the length-N DFT is a 2D N1 x N2 DFT with no twiddle
+// factors.  All the index maps are compile-time register renamings.
+template <class T, int N, int SIGN>
+__device__ __forceinline__ void fft_pfa(cplx<T> (&x)[N]) {
+  constexpr int N1 = pfa_first<N, SIGN>(), N2 = N / N1;
+  constexpr int Q2 = inv_mod<N2 % N1, N1>(), Q1 = inv_mod<N1 % N2, N2>();
+  cplx<T> a[N2][N1];
+  sfor<N1>([&](auto i1) {
+    sfor<N2>([&](auto i2) {
+      constexpr int n1 = decltype(i1)::value, n2 = decltype(i2)::value;
+      a[n2][n1] = x[(n1 * N2 + n2 * N1) % N];
+    });
+  });
+  sfor<N2>([&](auto i2) { fft<T, N1, SIGN>(a[decltype(i2)::value]); });
+  cplx<T> b[N1][N2];
+  sfor<N1>([&](auto i1) {
+    sfor<N2>([&](auto i2) { b[decltype(i1)::value][decltype(i2)::value] = a[decltype(i2)::value][decltype(i1)::value]; });
+  });
+  sfor<N1>([&](auto i1) { fft<T, N2, SIGN>(b[decltype(i1)::value]); });
+  sfor<N1>([&](auto i1) {
+    sfor<N2>([&](auto i2) {
+      constexpr int k1 = decltype(i1)::value, k2 = decltype(i2)::value;
+      x[(k1 * N2 * Q2 + k2 * N1 * Q1) % N] = b[k1][k2];
+    });
+  });
+}
+
 // In-place length-N DFT of x (decimation in time, fully unrolled).
 template <class T, int N, int SIGN>
 __device__ __forceinline__ void fft(cplx<T> (&x)[N]) {
-  constexpr int R = pick_radix<N, SIGN>();
-  if constexpr (R == N) {
+  constexpr int R = pick_radix<N>();
+  if constexpr (pfa_first<N, SIGN>() > 1) {
+    fft_pfa<T, N, SIGN>(x);
+  } else if constexpr (R == N) {
     bfly<T, N, SIGN>(x);
   } else {
     constexpr int M = N / R;
