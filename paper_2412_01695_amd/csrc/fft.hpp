@@ -156,19 +156,26 @@ __device__ __forceinline__ void bfly_odd(cplx<T> (&a)[R]) {
   sfor<H>([&](auto jj) { x0 = cadd(x0, s[decltype(jj)::value + 1]); });
   sfor<H>([&](auto kk) {
     constexpr int k = decltype(kk)::value + 1;
-    cplx<T> A = a0, B = {T(0), T(0)};
+    cplx<T> A = a0;
     sfor<H>([&](auto jj) {
       constexpr int j = decltype(jj)::value + 1;
       constexpr T c = T(ct::cos2pi(long(j) * k, R));
-      constexpr T sn = T(SIGN * ct::sin2pi(long(j) * k, R));
       A.x += s[j].x * c;
       A.y += s[j].y * c;
-      B.x += d[j].x * sn;
-      B.y += d[j].y * sn;
     });
-    // X_k = A + i B ; X_{R-k} = A - i B
-    a[k] = {A.x - B.y, A.y + B.x};
-    a[R - k] = {A.x + B.y, A.y - B.x};
+    // X_k = A + i B, X_{R-k} = A - i B with B = SIGN sum_j d_j sin(2 pi jk/R),
+    // each output accumulated from A so that every product fuses into an FMA
+    cplx<T> P = A, Q = A;
+    sfor<H>([&](auto jj) {
+      constexpr int j = decltype(jj)::value + 1;
+      constexpr T sn = T(SIGN * ct::sin2pi(long(j) * k, R));
+      P.x -= d[j].y * sn;
+      P.y += d[j].x * sn;
+      Q.x += d[j].y * sn;
+      Q.y -= d[j].x * sn;
+    });
+    a[k] = P;
+    a[R - k] = Q;
   });
   a[0] = x0;
 }
