@@ -13,10 +13,12 @@ Modules
   basis        plane-wave sphere per k (Sec. 2.2.1, sphere inequality)
   dft          separable 3D DFT exactly as written (Sec. 4, Eqs. zfft, yfft,
                xfft and fwFFT), evaluated as explicit sums (DFT matrices)
-  hamiltonian  dense H_k and two independent H|psi> routes (Sec. 2.2)
-  solvers      dense eigenpairs, the paper's Davidson steps (Sec. 2.1),
-               the paper's preconditioned CG (Sec. 2.4) and the closed-form
-               solution of the DFPT linear system (Sec. 2.3)
+  hamiltonian  dense H_k and two independent H|psi> routes (Sec. 2.2); the
+               overlap S_k and S|psi> by Eqs. delta_eq and finals
+  solvers      dense (generalized) eigenpairs, the paper's Davidson steps
+               (Sec. 2.1, with S), the paper's preconditioned CG (Sec. 2.4)
+               and the closed-form solution of the DFPT linear system
+               (Sec. 2.3, with S)
 
 Parity status: every function here is pinned by the CPU tests in
 tests/test_oracle_*.py against closed forms, invariants, brute force or

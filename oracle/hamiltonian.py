@@ -1,4 +1,5 @@
-"""Kohn-Sham Hamiltonian on the plane-wave basis (oracle; test infrastructure only).
+"""Kohn-Sham Hamiltonian and overlap on the plane-wave basis (oracle; test
+infrastructure only).
 
 Sec. 2.2: H = kinetic + local + nonlocal.
   kinetic   C'(G) = (1/2)|k+G|^2 C(G)                         (Sec. 2.2.1)
@@ -16,6 +17,13 @@ Two independent routes are provided:
   * ``h_psi_realspace`` follows the steps above literally for each band,
     with the naive separable DFT of ``oracle.dft``.
 Both agree for any mesh on which G -> m mod N is one-to-one.
+
+Sec. 2.2 (overlap) and Sec. 2.2.3: S = 1 + sum_mn q_mn |beta_m><beta_n|,
+applied from the same projections as the nonlocal term
+  delta_m = sum_n q_mn lambda_n                                  (Eq. delta_eq)
+  S C     = C + sum_m delta_m beta_m(k+G)                         (Eq. finals)
+``overlap_matrix`` writes S_k out; ``s_psi_projections`` follows the two
+equations literally.  With no q the overlap is the identity.
 """
 from __future__ import annotations
 
@@ -40,6 +48,24 @@ def local_matrix(miller: np.ndarray, fft, vt: np.ndarray) -> np.ndarray:
 def nonlocal_matrix(beta: np.ndarray, dij: np.ndarray) -> np.ndarray:
     """N[G, G'] = sum_mn beta_m(G) D_mn beta_n(G')^*  (beta is (nproj, npw))."""
     return beta.T @ dij @ beta.conj()
+
+
+def overlap_matrix(beta: np.ndarray, qij) -> np.ndarray:
+    """S[G, G'] = delta_GG' + sum_mn beta_m(G) q_mn beta_n(G')^*  (identity when qij is None)."""
+    npw = beta.shape[1]
+    s = np.eye(npw, dtype=np.complex128)
+    if qij is not None:
+        s += beta.T @ np.asarray(qij, dtype=np.complex128) @ beta.conj()
+    return s
+
+
+def s_psi_projections(beta: np.ndarray, qij, psi: np.ndarray) -> np.ndarray:
+    """S|psi> for (nbnd, npw) rows by Eqs. lambdah, delta_eq and finals."""
+    if qij is None:
+        return np.array(psi, dtype=np.complex128)
+    lam = beta.conj() @ psi.T                      # Eq. lambdah   (nproj, nbnd)
+    dlt = np.asarray(qij) @ lam                    # Eq. delta_eq
+    return psi + (beta.T @ dlt).T                  # Eq. finals
 
 
 def dense_h(kin: np.ndarray, miller: np.ndarray, fft, vt: np.ndarray, beta: np.ndarray,
@@ -75,7 +101,7 @@ def h_psi_realspace(kin, miller, fft, v_r, beta, dij, psi) -> np.ndarray:
 class KPoint:
     """Everything the oracle needs at one k: basis, kinetic, projectors, H_k."""
 
-    def __init__(self, cfg, ik: int, vt: np.ndarray, beta_fn, dij=None):
+    def __init__(self, cfg, ik: int, vt: np.ndarray, beta_fn, dij=None, qij=None):
         self.ik = ik
         self.k = np.asarray(cfg.kpts[ik], dtype=np.float64)
         self.miller, q2 = basis.sphere(cfg.lat, self.k, cfg.ecut_ry)
@@ -84,6 +110,15 @@ class KPoint:
         self.beta = beta_fn(cfg, ik, self.miller)
         self.dij = cfg.dij if dij is None else dij
         self.h = dense_h(self.kin, self.miller, cfg.fft, vt, self.beta, self.dij)
+        self.qij = getattr(cfg, "qij", None) if qij is None else qij
+        self._s = None
+
+    @property
+    def s(self) -> np.ndarray:
+        """S_k as an (npw, npw) complex128 matrix (built on first use)."""
+        if self._s is None:
+            self._s = overlap_matrix(self.beta, self.qij)
+        return self._s
 
 
 def h_psi(cfg, v_r, beta_fn, psi_by_k):

@@ -1,16 +1,18 @@
 """Eigenpairs and linear solves for one k-point (oracle; test infrastructure only).
 
 * ``lowest_eigpairs``: the plain definition of what Davidson returns, the
-  lowest nbnd eigenpairs of H_k (Eq. ks with S = I), by dense diagonalisation.
+  lowest nbnd eigenpairs of H_k psi = eps S_k psi (Eq. ks; S = I when no
+  overlap is given), by dense (generalized) diagonalisation.
 * ``davidson``: the block-Davidson steps of Sec. 2.1 in the paper's order,
   used to compare iteration behaviour (parity targets stay the dense values).
 * ``pcg``: the preconditioned conjugate gradient of Sec. 2.4 (Eqs. ax1,
   row2, row3, row4, updated, ax2, lambda, updatex, updater, updatedold).
 * ``dfpt_*``: the DFPT linear system of Eq. linear_system at q = 0 with
-  S = I and the valence projector of Eq. projector,
-      (H - eps_nu + alpha P_v) x = rhs,
-  its right-hand side -(1 - P_v) dV u_nu, the shift alpha and the
-  preconditioner of Sec. 2.4, and its exact solution.
+  the valence projector of Eq. projector,
+      (H - eps_nu S + alpha S P_v S) x = rhs,    P_v = sum_mu |u_mu><u_mu|
+  (S-orthonormal u), its right-hand side -(1 - S P_v) dV u_nu (dS = 0),
+  the shift alpha and the preconditioner of Sec. 2.4, and its exact
+  solution.  Without an overlap S = I.
 
 Readings where the paper is silent (units, stopping rules, alpha, the
 complex inner product of the CG) are the project's and are listed with the
@@ -19,11 +21,17 @@ design notes; each is stated again at the function that uses it.
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 
 
-def lowest_eigpairs(h: np.ndarray, nbnd: int):
-    """Lowest nbnd eigenvalues (Ha) and eigenvectors (npw, nbnd) of Hermitian h."""
-    w, v = np.linalg.eigh(h)
+def lowest_eigpairs(h: np.ndarray, nbnd: int, s: np.ndarray | None = None):
+    """Lowest nbnd eigenvalues (Ha) and eigenvectors (npw, nbnd) of Hermitian h,
+    or of the pencil (h, s) with s Hermitian positive definite (eigenvectors
+    then S-orthonormal)."""
+    if s is None:
+        w, v = np.linalg.eigh(h)
+    else:
+        w, v = scipy.linalg.eigh(h, s)
     return w[:nbnd], v[:, :nbnd]
 
 
@@ -40,43 +48,49 @@ def _reduced_eig(ht, st, nbnd, rcond=1e-9):
     return w[:nbnd], x @ y[:, :nbnd]
 
 
-def _orthonormal_complement(basis, corr, drop=1e-10):
+def _orthonormal_complement(basis, corr, s, drop=1e-10):
     """Normalised correction vectors (Sec. 2.1, normalisation step), made
-    orthogonal to the current basis and to each other first (two passes of
-    Gram-Schmidt) so the reduced overlap stays well conditioned; a vector
-    with nothing left after the projection is dropped."""
+    S-orthogonal to the current basis and to each other first (two passes of
+    Gram-Schmidt in the S inner product) so the reduced overlap stays well
+    conditioned; a vector with nothing left after the projection is dropped."""
+    def snorm(c):
+        return float(np.sqrt(np.real(np.vdot(c, s @ c))))
+
     out = []
     for j in range(corr.shape[1]):
         c = corr[:, j].copy()
-        n0 = np.linalg.norm(c)
+        n0 = snorm(c)
         for _ in range(2):
-            c -= basis @ (basis.conj().T @ c)
+            c -= basis @ (basis.conj().T @ (s @ c))
             for o in out:
-                c -= o * np.vdot(o, c)
-        n = np.linalg.norm(c)
+                c -= o * np.vdot(o, s @ c)
+        n = snorm(c)
         if n > drop * n0:
             out.append(c / n)
     return np.array(out).T if out else np.zeros((corr.shape[0], 0), dtype=corr.dtype)
 
 
 def davidson(h: np.ndarray, psi0: np.ndarray, nbnd: int, eps_th: float, max_iter: int = 200,
-             max_basis_factor: int = 4, res_tol: float | None = None):
-    """Sec. 2.1 Davidson for one k with S = I.
+             max_basis_factor: int = 4, res_tol: float | None = None, s: np.ndarray | None = None):
+    """Sec. 2.1 Davidson for one k, for H psi = eps S psi (S = I when s is None).
 
-    psi0: (nbnd, npw) starting vectors.  H_diag is the exact diagonal of h
-    and S_diag = 1.  A correction is added for every band whose eigenvalue
-    moved by more than eps_th (and, when ``res_tol`` is given, whose residual
-    norm is still above it); when the basis would exceed
-    max_basis_factor * nbnd vectors the basis restarts from the current Ritz
-    vectors.  Returns (eigenvalues, vectors (nbnd, npw), iterations)."""
+    psi0: (nbnd, npw) starting vectors.  H_diag and S_diag are the exact
+    diagonals of h and s.  A correction is added for every band whose
+    eigenvalue moved by more than eps_th (and, when ``res_tol`` is given,
+    whose residual norm |(H - eps S) phi| is still above it); when the basis
+    would exceed max_basis_factor * nbnd vectors the basis restarts from the
+    current Ritz vectors.  Returns (eigenvalues, vectors (nbnd, npw),
+    iterations); the vectors are S-orthonormal."""
+    sm = np.eye(h.shape[0], dtype=np.complex128) if s is None else s
     hdiag = np.real(np.diag(h))
+    sdiag = np.real(np.diag(sm))
     basis = np.array(psi0, dtype=np.complex128).T          # (npw, nbase)
     hb = h @ basis
+    sb = sm @ basis
     ht = basis.conj().T @ hb
-    st = basis.conj().T @ basis
+    st = basis.conj().T @ sb
     eps, v = _reduced_eig(ht, st, nbnd)
-    phi = basis @ v
-    hphi = hb @ v
+    phi, hphi, sphi = basis @ v, hb @ v, sb @ v
     todo = np.ones(nbnd, dtype=bool)
     it = 0
     for it in range(1, max_iter + 1):
@@ -84,32 +98,34 @@ def davidson(h: np.ndarray, psi0: np.ndarray, nbnd: int, eps_th: float, max_iter
         if idx.size == 0:
             break
         # correction vectors (H_diag - eps S_diag)^-1 (H - eps S) phi
-        res = hphi[:, idx] - phi[:, idx] * eps[idx][None, :]
-        den = hdiag[:, None] - eps[idx][None, :]
+        res = hphi[:, idx] - sphi[:, idx] * eps[idx][None, :]
+        den = hdiag[:, None] - eps[idx][None, :] * sdiag[:, None]
         den = np.where(np.abs(den) < 1e-2, np.where(den < 0, -1e-2, 1e-2), den)
         corr = res / den
         if basis.shape[1] + idx.size > max_basis_factor * nbnd:
-            basis, hb = phi.copy(), hphi.copy()
-        corr = _orthonormal_complement(basis, corr)
+            basis, hb, sb = phi.copy(), hphi.copy(), sphi.copy()
+        corr = _orthonormal_complement(basis, corr, sm)
         if corr.shape[1] == 0:
             break
         basis = np.concatenate([basis, corr], axis=1)
         hb = np.concatenate([hb, h @ corr], axis=1)
+        sb = np.concatenate([sb, sm @ corr], axis=1)
+        # extended reduced Hamiltonian and overlap, then the reduced problem
         ht = basis.conj().T @ hb
-        st = basis.conj().T @ basis
+        st = basis.conj().T @ sb
         new_eps, v = _reduced_eig(0.5 * (ht + ht.conj().T), 0.5 * (st + st.conj().T), nbnd)
-        phi = basis @ v
-        hphi = hb @ v
+        phi, hphi, sphi = basis @ v, hb @ v, sb @ v
         todo = np.abs(new_eps - eps) > eps_th
         if res_tol is not None:
-            rn = np.linalg.norm(hphi - phi * new_eps[None, :], axis=0)
+            rn = np.linalg.norm(hphi - sphi * new_eps[None, :], axis=0)
             todo |= rn > res_tol
         eps = new_eps
-    # final Rayleigh-Ritz on the nbnd Ritz vectors alone, with H applied
+    # final Rayleigh-Ritz on the nbnd Ritz vectors alone, with H and S applied
     # afresh: a well-conditioned reduced problem, so the returned eigenvalues
     # carry no round-off from nearly dependent basis vectors
     hphi = h @ phi
-    eps, v = _reduced_eig(phi.conj().T @ hphi, phi.conj().T @ phi, nbnd)
+    sphi = sm @ phi
+    eps, v = _reduced_eig(phi.conj().T @ hphi, phi.conj().T @ sphi, nbnd)
     return eps, (phi @ v).T, it
 
 
@@ -148,16 +164,23 @@ def dfpt_alpha(eps_occ: np.ndarray) -> float:
     return float(max(2.0 * (np.max(eps_occ) - np.min(eps_occ)), 0.1))
 
 
-def dfpt_matrix(h: np.ndarray, u_occ: np.ndarray, eps_nu: float, alpha: float) -> np.ndarray:
-    """A = H - eps_nu + alpha sum_mu |u_mu><u_mu|  (u_occ is (npw, nocc))."""
-    a = h - eps_nu * np.eye(h.shape[0]) + alpha * (u_occ @ u_occ.conj().T)
-    return a
+def dfpt_matrix(h: np.ndarray, u_occ: np.ndarray, eps_nu: float, alpha: float,
+                s: np.ndarray | None = None) -> np.ndarray:
+    """A = H - eps_nu S + alpha sum_mu S|u_mu><u_mu|S  (Eq. projector; u_occ is
+    (npw, nocc), S-orthonormal; S = I when s is None)."""
+    if s is None:
+        return h - eps_nu * np.eye(h.shape[0]) + alpha * (u_occ @ u_occ.conj().T)
+    su = s @ u_occ
+    return h - eps_nu * s + alpha * (su @ su.conj().T)
 
 
-def dfpt_rhs(dv_mat: np.ndarray, u_occ: np.ndarray) -> np.ndarray:
-    """rhs_nu = -(1 - P_v) dV u_nu restricted to the sphere, all nu: (npw, nocc)."""
+def dfpt_rhs(dv_mat: np.ndarray, u_occ: np.ndarray, s: np.ndarray | None = None) -> np.ndarray:
+    """rhs_nu = -(1 - S P_v) dV u_nu restricted to the sphere, all nu: (npw, nocc)
+    (the conduction projector of Eq. linear_system applied on the left, with
+    dS = 0; S = I when s is None)."""
     y = dv_mat @ u_occ
-    y = y - u_occ @ (u_occ.conj().T @ y)
+    su = u_occ if s is None else s @ u_occ
+    y = y - su @ (u_occ.conj().T @ y)
     return -y
 
 

@@ -69,6 +69,7 @@ class Config:
     dij: np.ndarray              # (nproj, nproj) complex Hermitian, Ha
     seed: int
     extra: dict = field(default_factory=dict)
+    qij: np.ndarray | None = None  # (nproj, nproj) complex Hermitian overlap coefficients; None: S = 1
 
     @property
     def omega(self) -> float:
@@ -113,6 +114,40 @@ def _d_two_channel() -> np.ndarray:
     return d
 
 
+def q_model(cfg: Config) -> np.ndarray:
+    """Model overlap coefficients q_pq (Ha-free, Hermitian, positive definite)
+    with the block structure of D: per atom, q = 16 on s and 12 on each p of
+    a single channel; with two radial channels the same (l, m) are coupled,
+    s [[16, 4], [4, 10]] and p [[12, 3], [3, 8]].  With these values the
+    projector term of S is of order 0.1 - 0.5, like an augmentation charge."""
+    n = cfg.nproj
+    q = np.zeros((n, n), dtype=np.complex128)
+    by_atom = {}
+    for i, pr in enumerate(cfg.projectors):
+        by_atom.setdefault(pr.atom, []).append(i)
+    for idx in by_atom.values():
+        rcs = sorted({cfg.projectors[i].rc for i in idx})
+        for i in idx:
+            pi = cfg.projectors[i]
+            for j in idx:
+                pj = cfg.projectors[j]
+                if pi.l != pj.l or pi.alpha != pj.alpha:
+                    continue
+                ci, cj = rcs.index(pi.rc), rcs.index(pj.rc)
+                blk = ((16.0, 4.0), (4.0, 10.0)) if pi.l == 0 else ((12.0, 3.0), (3.0, 8.0))
+                q[i, j] = blk[ci][cj]
+    return q
+
+
+def with_overlap(cfg: Config, qij=None) -> Config:
+    """The same workload with the overlap S = 1 + sum_pq |beta_p> q_pq <beta_q|
+    (`q_model` unless `qij` is given)."""
+    c = Config(cfg.name + "-uspp", cfg.lat, cfg.ecut_ry, cfg.fft, cfg.kpts, cfg.nbnd, cfg.tau,
+               cfg.projectors, cfg.dij, cfg.seed, dict(cfg.extra))
+    c.qij = q_model(cfg) if qij is None else np.asarray(qij, dtype=np.complex128)
+    return c
+
+
 def make_config(cid: int) -> Config:
     """The four batch workloads (ids 1..4); id 5 is the serving stream (`serving_requests`)."""
     lat = fcc_lattice()
@@ -140,7 +175,7 @@ def subset(cfg: Config, ks) -> Config:
     """Same crystal and cutoff on a subset of the k-list (indices `ks`)."""
     ks = np.asarray(ks, dtype=np.int64)
     c = Config(cfg.name + f"-sub{len(ks)}", cfg.lat, cfg.ecut_ry, cfg.fft, cfg.kpts[ks].copy(),
-               cfg.nbnd, cfg.tau, cfg.projectors, cfg.dij, cfg.seed, dict(cfg.extra))
+               cfg.nbnd, cfg.tau, cfg.projectors, cfg.dij, cfg.seed, dict(cfg.extra), cfg.qij)
     c.extra["k_index"] = ks
     return c
 

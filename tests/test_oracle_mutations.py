@@ -2,15 +2,18 @@
 
 Each case patches one plausible slip into the oracle (a flipped sign, a
 transposed index, a dropped conjugate, a missing normalisation, a wrong
-kinetic factor, a wrong CG step) and checks that at least one pin test
+kinetic factor, a wrong CG step, a transposed or unconjugated overlap term,
+the overlap left out of a residual or a projector) and checks that at least one pin test
 then fails."""
 import numpy as np
 import pytest
 
 from oracle import basis, dft, hamiltonian as ham, solvers
+from paper_2412_01695_amd import synth
 
 import test_oracle_dft as tdft
 import test_oracle_hamiltonian as tham
+import test_oracle_overlap as tovl
 import test_oracle_solvers as tsol
 
 
@@ -63,3 +66,47 @@ def test_wrong_cg_step_sign_is_caught(monkeypatch):
 
     monkeypatch.setattr(solvers, "pcg", bad)
     assert _fails(tsol.test_pcg_on_a_small_spd_system)
+
+
+def test_transposed_q_is_caught(monkeypatch):
+    orig = ham.overlap_matrix
+    monkeypatch.setattr(ham, "overlap_matrix", lambda beta, q: orig(beta, None if q is None else np.asarray(q).T))
+    assert _fails(tovl.test_overlap_inverse_by_woodbury)
+
+
+def test_dropped_overlap_conjugate_is_caught(monkeypatch):
+    def bad(beta, q):
+        s = np.eye(beta.shape[1], dtype=np.complex128)
+        return s if q is None else s + beta.T @ np.asarray(q) @ beta
+    monkeypatch.setattr(ham, "overlap_matrix", bad)
+    assert _fails(tovl.test_overlap_inverse_by_woodbury)
+
+
+def test_overlap_left_out_of_the_residual_is_caught(monkeypatch):
+    orig = solvers.davidson
+
+    def bad(h, psi0, nbnd, eps_th, max_iter=200, max_basis_factor=4, res_tol=None, s=None):
+        return orig(h, psi0, nbnd, eps_th, max_iter, max_basis_factor, res_tol, None)
+
+    monkeypatch.setattr(solvers, "davidson", bad)
+    assert _fails(tovl.test_generalized_davidson_reaches_dense_eigenvalues, _c1s())
+
+
+def test_valence_projector_without_overlap_is_caught(monkeypatch):
+    orig = solvers.dfpt_matrix
+    monkeypatch.setattr(solvers, "dfpt_matrix",
+                        lambda h, u, e, a, s=None: orig(h, u, e, a, None) + e * (np.eye(h.shape[0]) - s))
+    assert _fails(tovl.test_dfpt_with_overlap_closed_form, _c1s())
+
+
+def test_conduction_projector_without_overlap_is_caught(monkeypatch):
+    orig = solvers.dfpt_rhs
+    monkeypatch.setattr(solvers, "dfpt_rhs", lambda dv, u, s=None: orig(dv, u, None))
+    assert _fails(tovl.test_dfpt_with_overlap_closed_form, _c1s())
+
+
+def _c1s():
+    cfg = synth.with_overlap(synth.make_config(1))
+    v = synth.vloc_grid(cfg)
+    vt = ham.vtilde(v)
+    return cfg, v, [ham.KPoint(cfg, ik, vt, tovl.beta_fn) for ik in range(cfg.nk)]
