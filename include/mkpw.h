@@ -81,8 +81,8 @@ pw_status pw_set_option(pw_ctx* ctx, const char* key, int64_t value);
 
 /* Read an option (the keys above), or "hpsi_variant_tuned" / "hpsi_slab_tuned" /
  * "hpsi_threads_tuned" (the shape of this context's last H|psi> launch, 0 if
- * none),
- * or "device_bytes" (device memory the context holds now). */
+ * none), "device_bytes" (device memory the context holds now) or "overlap"
+ * (1 while overlap coefficients q are set, else 0). */
 pw_status pw_get_option(const pw_ctx* ctx, const char* key, int64_t* value);
 
 /* Direct lattice, rows a1, a2, a3 in bohr (host, 9 doubles).  Resets the
@@ -120,6 +120,18 @@ pw_status pw_set_vloc(pw_ctx* ctx, const double* v_r);
  * nonlocal term.  nproj <= 32. */
 pw_status pw_set_projectors(pw_ctx* ctx, int nproj, const void* beta, const void* dij);
 
+/* Overlap coefficients q_pq (Sec. 2.2, overlap operator of ultrasoft and PAW
+ * pseudopotentials): S = 1 + sum_pq |beta_p> q_pq <beta_q| with the
+ * projectors of pw_set_projectors.  qij: host complex128 nproj x nproj,
+ * Hermitian to 1e-12 relative (else PW_EINVAL); NULL removes the overlap
+ * (S = 1).  Needs projectors (nproj > 0) set first (else PW_ESTATE);
+ * pw_set_projectors and pw_set_kpoints remove it.  With an overlap set,
+ * pw_davidson solves H psi = eps S psi and pw_dfpt_cg uses
+ * A = H - eps S + alpha S P_v S.  S must be positive definite (it is when q
+ * is positive semidefinite); the solvers report PW_EINVAL when the basis
+ * Gram matrix in the S inner product is not. */
+pw_status pw_set_qij(pw_ctx* ctx, const void* qij);
+
 /* Random starting vectors for pw_davidson, drawn on the device:
  * psi(k, b, G) = (x + i y) / (1 + |k+G|^2/2), normalised per band, x and y
  * two N(0, 1) values (Box-Muller) from the SplitMix64 finaliser chained over
@@ -136,12 +148,21 @@ pw_status pw_init_guess(pw_ctx* ctx, int nbnd, uint64_t seed, void* psi);
  * complex64 for PW_MIXED; they must not overlap. */
 pw_status pw_h_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* hpsi);
 
-/* Lowest nbnd eigenpairs of H at every k by block Davidson (Sec. 2.1),
- * all k-points advancing together, each stopping on its own.
+/* Spsi = S psi for every k-point and band at once (Sec. 2.2 overlap
+ * operator, Eqs. lambdah, delta_eq, finals): psi + sum_p delta_p beta_p with
+ * delta_p = sum_q q_pq <beta_q|psi>; a copy of psi when no overlap is set.
+ * psi and spsi: device, (nk, nbnd, npwx); complex128 for PW_FP64,
+ * complex64 for PW_MIXED (FP32 arithmetic); spsi may be psi itself (in
+ * place), otherwise they must not overlap.  Padding written as zero. */
+pw_status pw_s_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* spsi);
+
+/* Lowest nbnd eigenpairs of H psi = eps S psi at every k by block Davidson
+ * (Sec. 2.1; S = 1 without an overlap), all k-points advancing together,
+ * each stopping on its own.
  * psi: device complex128 (nk, nbnd, npwx): starting vectors in, eigenvectors
- * out (orthonormal).  eig_ha: host (nk, nbnd) doubles, eigenvalues in Ha.
+ * out (S-orthonormal).  eig_ha: host (nk, nbnd) doubles, eigenvalues in Ha.
  * A k-point is converged when every band's eigenvalue changed by less than
- * tol_ry/2 Ha in the last iteration and its residual norm |H psi - e psi| is
+ * tol_ry/2 Ha in the last iteration and its residual norm |H psi - e S psi| is
  * below max(1e-5, sqrt(tol_ry)) (so the eigenvalue error is of order
  * residual^2 / gap).  iters, converged: host (nk) ints, may be NULL.
  * PW_MIXED applies H in complex64 until convergence, then refines in FP64
@@ -151,10 +172,11 @@ pw_status pw_davidson(pw_ctx* ctx, pw_prec prec, int nbnd, void* psi, double* ei
                 int max_iter, int32_t* iters, int32_t* converged);
 
 /* Batched preconditioned CG (Sec. 2.4) for the DFPT linear systems
- * (Eq. linear_system at q = 0 with S = I and the valence projector of
- * Eq. projector):  (H - eps_{k,nu} + alpha_k P_v) x_{k,nu} = rhs_{k,nu},
- * P_v = sum_{mu<nocc} |u_mu><u_mu|, one system per (k, nu), nu < nrhs.
- * psi_occ: device complex128 (nk, nocc, npwx) orthonormal u.
+ * (Eq. linear_system at q = 0 with the valence projector of Eq. projector):
+ * (H - eps_{k,nu} S + alpha_k S P_v S) x_{k,nu} = rhs_{k,nu},
+ * P_v = sum_{mu<nocc} |u_mu><u_mu|, one system per (k, nu), nu < nrhs
+ * (S = 1 without an overlap).
+ * psi_occ: device complex128 (nk, nocc, npwx) S-orthonormal u.
  * eps_ha: host (nk, nrhs) doubles.  alpha_ha: host (nk) doubles, > 0.
  * rhs: device complex128 (nk, nrhs, npwx).  dpsi: device complex128
  * (nk, nrhs, npwx): initial guess in, solution out.

@@ -1,10 +1,14 @@
 // Batched preconditioned conjugate gradient for the DFPT linear systems
-// (Sec. 2.3 Eq. linear_system at q = 0 with S = I, the valence projector of
+// (Sec. 2.3 Eq. linear_system at q = 0, the valence projector of
 // Eq. projector, and the CG recurrence of Sec. 2.4, Eqs. ax1 .. updatedold),
 // one system per (k-point, band), all of them advancing in the same launches
 // (Sec. 3, Algorithm phonon_new).  Converged systems are frozen.
 //
-//   A x = H x - eps_nu x + alpha_k U (U^H x),   U = occupied states at k
+//   A x = H x - eps_nu S x + alpha_k SU (SU^H x),   U = occupied states at k
+//   (S = 1 without an overlap; with one, SU = S U is formed once, so the
+//   projector term of Eqs. compute_mu, use_mu and apply_s_ch costs two
+//   small products per application, and -eps S x is accumulated into H x by
+//   the overlap kernel)
 //   r = A x - b;  loop:  d = M^-1 r;  rho = Re(d^H r);  stop if |rho| < thr;
 //                        (from the 2nd iteration) d += (rho/rho_old) d_old;
 //                        t = A d;  lambda = -Re(d^H r) / Re(d^H t);
@@ -65,12 +69,14 @@ __global__ void scale_w_kernel(cd* W, int n, const double* alpha) {
   }
 }
 
-// r = t - eps x - b  (t = H x + alpha U U^H x);  every system restarts as active
+// r = t - eps x - b  (t = H x + alpha U U^H x), or r = t - b when t already
+// holds the -eps S x term;  every system restarts as active
 __global__ __launch_bounds__(256) void init_resid_kernel(const cd* t, const cd* x, const cd* b, const double* eps,
-                                                         cd* r, int npwx, int* active, const int* npw, int nrhs) {
+                                                         cd* r, int npwx, int* active, const int* npw, int nrhs,
+                                                         int sub_eps) {
   const long sys = blockIdx.x;
   const int k = (int)(sys / nrhs);
-  const double e = eps[sys];
+  const double e = sub_eps ? eps[sys] : 0.0;
   const long o = sys * npwx;
   for (int g = threadIdx.x; g < npwx; g += 256) {
     cd v = {0.0, 0.0};
@@ -120,16 +126,17 @@ __global__ __launch_bounds__(256) void step1_kernel(const cd* r, cd* d, const cd
   if (threadIdx.x == 0) rho[sys] = s;
 }
 
-// t -= eps d ; lambda = -Re(d^H r)/Re(d^H t) ; x += lambda d ; r += lambda t ; d_old = d ; rho_old = rho
+// t -= eps d (when sub_eps) ; lambda = -Re(d^H r)/Re(d^H t) ; x += lambda d ;
+// r += lambda t ; d_old = d ; rho_old = rho
 __global__ __launch_bounds__(256) void step2_kernel(cd* t, const cd* d, cd* dold, cd* x, cd* r, const double* eps,
                                                     const int* npw, int npwx, int nrhs, const double* rho,
-                                                    double* rho_old, const int* active) {
+                                                    double* rho_old, const int* active, int sub_eps) {
   const long sys = blockIdx.x;
   if (!active[sys]) return;
   const int k = (int)(sys / nrhs);
   __shared__ double red[4];
   const long o = sys * npwx;
-  const double e = eps[sys];
+  const double e = sub_eps ? eps[sys] : 0.0;
   double dr = 0.0, dt = 0.0;
   for (int g = threadIdx.x; g < npw[k]; g += 256) {
     cd tv = {t[o + g].x - e * d[o + g].x, t[o + g].y - e * d[o + g].y};
@@ -223,6 +230,18 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
   CHIP(c, hipMemsetAsync(rho_old, 0, sizeof(double) * nsys, st));
   hipLaunchKernelGGL(tkin_kernel, dim3(nrhs, nk), dim3(256), 0, st, U, nocc, c->d_kin, c->d_npw, npwx, nrhs, tk);
   CTRY(check_launch(c, "tkin", st));
+  // P = S U for the projector term (U itself without an overlap)
+  const bool gen = c->have_q;
+  const cd* P = U;
+  if (gen) {
+    cd* SU;
+    CTRY(bf.get((size_t)nk * nocc * npwx, &SU));
+    VecSel sel;
+    sel.nvec = nocc;
+    sel.kstride = (long)nocc * npwx;
+    CTRY(launch_spsi(c, PW_FP64, sel, U, SU, nullptr, 0.0, st));
+    P = SU;
+  }
 
   bool fp64_h = prec == PW_FP64;
   // t = H v + alpha U (U^H v) for all systems
@@ -240,8 +259,9 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
       CTRY(launch_hpsi(c, PW_MIXED, sel, v32, t32, st));
       CTRY(launch_to_c128(c, t32, (long)nrhs * npwx, nullptr, t, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
     }
+    if (gen) CTRY(launch_spsi(c, PW_FP64, sel, v, t, eps, -1.0, st));  // t -= eps S v
     GramArgs g;
-    g.A = U; g.a_kstride = (long)nocc * npwx; g.a_n = nocc;
+    g.A = P; g.a_kstride = (long)nocc * npwx; g.a_n = nocc;
     g.B = v; g.b_kstride = (long)nrhs * npwx; g.b_n = nrhs;
     g.ld = npwx; g.npw = c->d_npw;
     g.C = W; g.c_kstride = (long)nocc * nrhs; g.ldc = nrhs;
@@ -250,7 +270,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     CTRY(check_launch(c, "scale_w", st));
     if (nocc > 64) return set_err(c, PW_EINVAL, "nocc must be <= 64");
     CombArgs m;
-    m.X = U; m.x_kstride = (long)nocc * npwx; m.x_n = nocc;
+    m.X = P; m.x_kstride = (long)nocc * npwx; m.x_n = nocc;
     m.Y = t; m.y_kstride = (long)nrhs * npwx; m.y_n = nrhs;
     m.ld = npwx; m.Cm = W; m.c_kstride = (long)nocc * nrhs; m.ldc = nrhs;
     m.accumulate = 1;
@@ -260,7 +280,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
   auto restart = [&]() -> pw_status {
     CTRY(apply_a(x, nullptr));
     hipLaunchKernelGGL(init_resid_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, x, b, eps, r, npwx, active,
-                       c->d_npw, nrhs);
+                       c->d_npw, nrhs, gen ? 0 : 1);
     return check_launch(c, "init_resid", st);
   };
 
@@ -300,7 +320,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     first = 0;
     CTRY(apply_a(d, active));
     hipLaunchKernelGGL(step2_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, d, dold, x, r, eps, c->d_npw, npwx,
-                       nrhs, rho, rho_old, active);
+                       nrhs, rho, rho_old, active, gen ? 0 : 1);
     CTRY(check_launch(c, "cg_step2", st));
   }
   CHIP(c, hipStreamSynchronize(st));

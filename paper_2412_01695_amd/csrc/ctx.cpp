@@ -126,6 +126,15 @@ namespace {
     }                                                                                    \
   } while (0)
 
+void clear_q(pw_ctx* c) {
+  for (void** p : {&c->d_q64, &c->d_q32}) {
+    dev_free(c, *p);
+    *p = nullptr;
+  }
+  c->have_q = false;
+  c->qij.clear();
+}
+
 void free_kdata(pw_ctx* c) {
   for (void** p : {(void**)&c->d_npw, (void**)&c->d_nstick, (void**)&c->d_gmap, (void**)&c->d_sof,
                    (void**)&c->d_kin, (void**)&c->d_mkey, (void**)&c->d_beta64, (void**)&c->d_beta32}) {
@@ -135,6 +144,7 @@ void free_kdata(pw_ctx* c) {
   c->have_k = false;
   c->have_proj = false;
   c->nproj = 0;
+  clear_q(c);
 }
 
 void free_all(pw_ctx* c) {
@@ -262,6 +272,7 @@ pw_status pw_get_option(const pw_ctx* c, const char* key, int64_t* value) {
   else if (k == "hpsi_slab_tuned") *value = c->last_hpsi_slab;
   else if (k == "hpsi_threads_tuned") *value = c->last_hpsi_threads;
   else if (k == "tune_log") *value = c->tune_log;
+  else if (k == "overlap") *value = c->have_q ? 1 : 0;
   else if (k == "device_bytes") {
     int64_t b = 0;
     for (auto& m : c->owned) b += (int64_t)m.bytes;
@@ -532,6 +543,7 @@ pw_status pw_set_projectors(pw_ctx* c, int nproj, const void* beta, const void* 
   for (size_t i = 0; i < 2 * nb; ++i)
     if (!std::isfinite(bsrc[i])) return set_err(c, PW_EINVAL, "projector array has a non-finite value");
   c->dij.assign(d, d + 2 * (size_t)nproj * nproj);
+  clear_q(c);
   if (c->host_only) {
     c->nproj = nproj;
     c->have_proj = true;
@@ -575,6 +587,46 @@ pw_status pw_set_projectors(pw_ctx* c, int nproj, const void* beta, const void* 
   }
   c->nproj = nproj;
   c->have_proj = true;
+  return PW_OK;
+}
+
+pw_status pw_set_qij(pw_ctx* c, const void* qij) {
+  if (!c) return PW_EINVAL;
+  if (!qij) {
+    clear_q(c);
+    return PW_OK;
+  }
+  if (!c->have_proj || c->nproj == 0) return set_err(c, PW_ESTATE, "set projectors (nproj > 0) before q");
+  const int n = c->nproj;
+  const double* q = (const double*)qij;
+  double qmax = 0.0, herm = 0.0;
+  for (int p = 0; p < n; ++p)
+    for (int r = 0; r < n; ++r) {
+      double re = q[2 * (p * n + r)], im = q[2 * (p * n + r) + 1];
+      double rt = q[2 * (r * n + p)], it = q[2 * (r * n + p) + 1];
+      if (!std::isfinite(re) || !std::isfinite(im)) return set_err(c, PW_EINVAL, "q has a non-finite value");
+      qmax = std::max(qmax, std::hypot(re, im));
+      herm = std::max(herm, std::hypot(re - rt, im + it));
+    }
+  if (herm > 1e-12 * std::max(qmax, 1e-300) && herm > 0) return set_err(c, PW_EINVAL, "q is not Hermitian");
+  clear_q(c);
+  c->qij.assign(q, q + 2 * (size_t)n * n);
+  if (c->host_only) {
+    c->have_q = true;
+    return PW_OK;
+  }
+  (void)hipSetDevice(c->device);
+  std::vector<float> q32(2 * (size_t)n * n);
+  for (size_t i = 0; i < q32.size(); ++i) q32[i] = (float)q[i];
+  pw_status s;
+  double* p64 = nullptr;
+  float* p32 = nullptr;
+  if ((s = upload(c, q, 2 * (size_t)n * n, &p64)) != PW_OK) return s;
+  c->d_q64 = p64;
+  if ((s = upload(c, q32.data(), q32.size(), &p32)) != PW_OK) return s;
+  c->d_q32 = p32;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->have_q = true;
   return PW_OK;
 }
 

@@ -2,17 +2,20 @@
 // many-k form of Sec. 3, Algorithm new_gpu: every k-point of the context
 // advances in the same launches and stops on its own).
 //
-// Per k-point the basis is kept orthonormal in FP64, so the reduced problem
+// The problem is H psi = eps S psi (S = 1 without an overlap).  Per k-point
+// the basis is kept S-orthonormal in FP64, so the reduced problem
 // (H~ - eps S~) v = 0 of Sec. 2.1 has S~ = I and is solved by the batched
-// Jacobi eigensolver.  One iteration:
-//   X = V C, HX = HV C            Ritz vectors of the current basis
-//   R = HX - theta X, |R|          residuals
+// Hermitian eigensolver.  SV = S V is carried along with V (updated by the
+// same row operations), so S is applied once per new vector.  One iteration:
+//   X = V C, HX = HV C, SX = S X             Ritz vectors of the current basis
+//   R = HX - theta SX, |R|                   residuals
 //   converged band: |theta - theta_prev| < tol and |R| < rtol
-//   T = R / (H_diag - theta)       correction vectors for the others (Sec. 2.1,
-//                                  with S_diag = 1 and a 1e-2 Ha guard on the
-//                                  denominator)
-//   if N_base + N_nc > N_max:  restart from the Ritz vectors (V = X, HV = HX)
-//   T <- T - V (V^H T) twice, normalise, Cholesky-orthonormalise twice
+//   T = R / (H_diag - theta S_diag)          correction vectors for the others
+//                                            (Sec. 2.1, with a 1e-2 Ha guard
+//                                            on the denominator)
+//   if N_base + N_nc > N_max:  restart from the Ritz vectors (V = X, ...)
+//   ST = S T; T <- T - V (SV^H T) twice, normalise, Cholesky-orthonormalise
+//   in the S inner product twice
 //   HT = H T  (pw_h_psi kernels on the new rows only; complex64 in the
 //              mixed-precision phase)
 //   extend H~ by V^H HT, diagonalise -> theta, C
@@ -47,12 +50,13 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // H_diag(k, G) = |k+G|^2/2 + V~(0) + Re sum_pq beta_p D_pq beta_q^*
+// S_diag(k, G) = 1 + Re sum_pq beta_p q_pq beta_q^*   (qij null: 1)
 __global__ void hdiag_kernel(const int* npw, int npwx, const double* kin, double v0, int nproj, const cd* beta,
-                             const cd* dij, double* hd) {
+                             const cd* dij, const cd* qij, double* hd, double* sd) {
   const int k = blockIdx.y;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= npwx) return;
-  double h = 0.0;
+  double h = 0.0, s = 1.0;
   if (g < npw[k]) {
     h = kin[(long)k * npwx + g] + v0;
     const cd* b = beta + (long)k * nproj * npwx;
@@ -64,16 +68,22 @@ __global__ void hdiag_kernel(const int* npw, int npwx, const double* kin, double
         // Re(bp * d * conj(bq))
         double tr = bp.x * d.x - bp.y * d.y, ti = bp.x * d.y + bp.y * d.x;
         h += tr * bq.x + ti * bq.y;
+        if (qij) {
+          cd e = qij[p * nproj + q];
+          double ur = bp.x * e.x - bp.y * e.y, ui = bp.x * e.y + bp.y * e.x;
+          s += ur * bq.x + ui * bq.y;
+        }
       }
     }
   }
   hd[(long)k * npwx + g] = h;
+  sd[(long)k * npwx + g] = s;
 }
 
 // residuals and corrections of the nbnd Ritz pairs of every active k
-__global__ __launch_bounds__(256) void resid_kernel(const cd* X, const cd* HX, const double* theta, const int* active,
-                                                    const double* hd, const int* npw, int npwx, int nbnd, cd* T,
-                                                    cd* R, double* rnorm) {
+__global__ __launch_bounds__(256) void resid_kernel(const cd* SX, const cd* HX, const double* theta, const int* active,
+                                                    const double* hd, const double* sd, const int* npw, int npwx,
+                                                    int nbnd, cd* T, cd* R, double* rnorm) {
   const int k = blockIdx.y, j = blockIdx.x;
   if (!active[k]) return;
   __shared__ double red[4];
@@ -84,10 +94,10 @@ __global__ __launch_bounds__(256) void resid_kernel(const cd* X, const cd* HX, c
   for (int g = threadIdx.x; g < npwx; g += 256) {
     cd t = {0.0, 0.0};
     if (g < n) {
-      cd x = X[row + g], hx = HX[row + g];
+      cd x = SX[row + g], hx = HX[row + g];
       cd r = {hx.x - th * x.x, hx.y - th * x.y};
       s += r.x * r.x + r.y * r.y;
-      double den = hd[(long)k * npwx + g] - th;
+      double den = hd[(long)k * npwx + g] - th * sd[(long)k * npwx + g];
       if (fabs(den) < 1e-2) den = den < 0 ? -1e-2 : 1e-2;
       t = {r.x / den, r.y / den};
       R[row + g] = r;
@@ -111,9 +121,9 @@ __global__ void gather_rows_kernel(const cd* T, int nbnd, cd* V, int nbmax, cons
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < npwx; g += gridDim.x * blockDim.x) dst[g] = src[g];
 }
 
-// restart: V[0:nbnd] = X, HV[0:nbnd] = HX, H~ = diag(theta)
-__global__ void restart_kernel(const int* flag, const cd* X, const cd* HX, cd* V, cd* HV, int nbnd, int nbmax,
-                               int npwx, cd* Hr, const double* theta) {
+// restart: V[0:nbnd] = X, HV[0:nbnd] = HX (and SV = SX when SX is given), H~ = diag(theta)
+__global__ void restart_kernel(const int* flag, const cd* X, const cd* HX, const cd* SX, cd* V, cd* HV, cd* SV,
+                               int nbnd, int nbmax, int npwx, cd* Hr, const double* theta) {
   const int k = blockIdx.y;
   if (!flag[k]) return;
   const long n = (long)nbnd * npwx;
@@ -124,6 +134,7 @@ __global__ void restart_kernel(const int* flag, const cd* X, const cd* HX, cd* V
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
     vd[e] = xs[e];
     hd[e] = hs[e];
+    if (SX) SV[(long)k * nbmax * npwx + e] = SX[(long)k * n + e];
   }
   if (blockIdx.x == 0) {
     cd* h = Hr + (long)k * nbmax * nbmax;
@@ -134,10 +145,11 @@ __global__ void restart_kernel(const int* flag, const cd* X, const cd* HX, cd* V
   }
 }
 
-// normalise rows [off, off + cnt) of each k
-// norms of rows [off, off + cnt) of each k into nrm[k * ldn + r]; scaled to unit norm when scale != 0
-__global__ __launch_bounds__(256) void normalize_rows_kernel(cd* V, long kstride, const int* off, const int* cnt,
-                                                             int npwx, double* nrm, int ldn, int scale) {
+// norms of rows [off, off + cnt) of each k into nrm[k * ldn + r]; scaled to unit
+// norm when scale != 0, the same rows of V2 (if given) by the same factor
+__global__ __launch_bounds__(256) void normalize_rows_kernel(cd* V, cd* V2, long kstride, const int* off,
+                                                             const int* cnt, int npwx, double* nrm, int ldn,
+                                                             int scale) {
   const int k = blockIdx.y, r = blockIdx.x;
   if (r >= cnt[k]) return;
   __shared__ double red[4];
@@ -149,6 +161,10 @@ __global__ __launch_bounds__(256) void normalize_rows_kernel(cd* V, long kstride
   if (!scale) return;
   const double f = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
   for (int g = threadIdx.x; g < npwx; g += 256) v[g] = {v[g].x * f, v[g].y * f};
+  if (V2) {
+    cd* w = V2 + (long)k * kstride + (long)(off[k] + r) * npwx;
+    for (int g = threadIdx.x; g < npwx; g += 256) w[g] = {w[g].x * f, w[g].y * f};
+  }
 }
 
 // copy rows [0, nbnd) of src (nbnd rows per k) into rows [0, nbnd) of dst (dst_rows per k)
@@ -203,15 +219,24 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   const double tol = 0.5 * tol_ry;  // Ha
   const double rtol64 = 1e-5;
   const double tol32 = std::max(tol, 2e-6), rtol32 = 2e-4;
+  const bool gen = c->have_q;  // generalized problem: S != 1
   Buf b(c);
   cd *V, *HV, *X, *HX, *T, *Rb, *Hr, *Cr, *Om, *Sm, *Mm;
-  double *theta, *rn, *hd, *nrm0, *nrm1;
+  cd *SV, *SX;
+  double *theta, *rn, *hd, *sd, *nrm0, *nrm1;
   int *d_nb, *d_nnc, *d_map, *d_flag, *d_active, *d_info, *d_zero, *d_nr, *d_ny, *d_ntot, *d_mask;
   const size_t kb = (size_t)nk * nbmax * npwx, kn = (size_t)nk * nbnd * npwx;
   TRY(b.get(kb, &V));
   TRY(b.get(kb, &HV));
   TRY(b.get(kn, &X));
   TRY(b.get(kn, &HX));
+  if (gen) {
+    TRY(b.get(kb, &SV));
+    TRY(b.get(kn, &SX));
+  } else {
+    SV = V;  // S = 1: the S-images are the vectors themselves
+    SX = X;
+  }
   TRY(b.get(kn, &T));
   TRY(b.get(kn, &Rb));
   TRY(b.get((size_t)nk * nbmax * nbmax, &Hr));
@@ -222,6 +247,7 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   TRY(b.get((size_t)nk * nbnd, &theta));
   TRY(b.get((size_t)nk * nbnd, &rn));
   TRY(b.get((size_t)nk * npwx, &hd));
+  TRY(b.get((size_t)nk * npwx, &sd));
   TRY(b.get((size_t)nk * nbnd, &nrm0));
   TRY(b.get((size_t)nk * nbnd, &nrm1));
   TRY(b.get((size_t)nk, &d_nb));
@@ -266,9 +292,20 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     dim3 grid((npwx + 255) / 256, nk);
     const int np = c->have_proj ? c->nproj : 0;
     hipLaunchKernelGGL(hdiag_kernel, grid, dim3(256), 0, st, c->d_npw, npwx, c->d_kin, c->v0, np,
-                       (const cd*)c->d_beta64, (const cd*)c->d_dij64, hd);
+                       (const cd*)c->d_beta64, (const cd*)c->d_dij64, gen ? (const cd*)c->d_q64 : nullptr, hd, sd);
     TRY(check_launch(c, "hdiag", st));
   }
+
+  // SV = S V on rows [nb, nb + nnc) (generalized problem only)
+  auto apply_s = [&](int nvec_max) -> pw_status {
+    if (!gen || nvec_max <= 0) return PW_OK;
+    VecSel sel;
+    sel.nvec = nvec_max;
+    sel.kstride = (long)nbmax * npwx;
+    sel.off = d_nb;
+    sel.cnt = d_nnc;
+    return launch_spsi(c, PW_FP64, sel, V, SV, nullptr, 0.0, st);
+  };
 
   // apply H to rows [nb, nb + nnc) of V into HV (FP64 or complex64 staging)
   bool fp64_h = (prec == PW_FP64);
@@ -293,17 +330,19 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     return PW_OK;
   };
 
-  // rows [nb, nb + nnc): remove the components along rows [0, nb) (twice) and
-  // normalise; the norms before (nrm0) and after (nrm1) the projection are kept
+  // rows [nb, nb + nnc): remove the components along rows [0, nb) in the S
+  // inner product (twice) and normalise; the norms before (nrm0) and after
+  // (nrm1) the projection are kept.  SV follows every row operation on V.
+  cd* SV2 = gen ? SV : nullptr;
   auto project = [&](int nb_max, int nnc_max) -> pw_status {
     if (nnc_max <= 0) return PW_OK;
     dim3 grid(nnc_max, nk);
-    hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, (long)nbmax * npwx, d_nb, d_nnc, npwx, nrm0,
-                       nbnd, 0);
+    hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, SV2, (long)nbmax * npwx, d_nb, d_nnc, npwx,
+                       nrm0, nbnd, 0);
     TRY(check_launch(c, "norm", st));
     for (int pass = 0; pass < 2 && nb_max > 0; ++pass) {
       GramArgs g;
-      g.A = V; g.a_kstride = (long)nbmax * npwx; g.a_off = d_zero; g.a_cnt = d_nb;
+      g.A = SV; g.a_kstride = (long)nbmax * npwx; g.a_off = d_zero; g.a_cnt = d_nb;
       g.B = V; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = d_nnc;
       g.ld = npwx; g.npw = c->d_npw;
       g.C = Om; g.c_kstride = (long)nbmax * nbnd; g.ldc = nbnd;
@@ -314,25 +353,32 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
       m.ld = npwx; m.Cm = Om; m.c_kstride = (long)nbmax * nbnd; m.ldc = nbnd;
       m.alpha = -1.0; m.accumulate = 1;
       TRY(launch_combine(c, m, nb_max, st));
+      if (gen) {
+        m.X = SV;
+        m.Y = SV;
+        TRY(launch_combine(c, m, nb_max, st));
+      }
     }
-    hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, (long)nbmax * npwx, d_nb, d_nnc, npwx, nrm1,
-                       nbnd, 1);
+    hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, SV2, (long)nbmax * npwx, d_nb, d_nnc, npwx,
+                       nrm1, nbnd, 1);
     return check_launch(c, "normalize", st);
   };
 
-  // Cholesky-orthonormalise rows [nb, nb + nnc) among themselves (twice); a k
-  // whose block is numerically dependent drops its new rows and restarts next time
+  // Cholesky-orthonormalise rows [nb, nb + nnc) among themselves in the S inner
+  // product (twice); a k whose block is numerically dependent drops its new rows
+  // and restarts next time
   auto cholqr = [&](int nnc_max) -> pw_status {
     if (nnc_max <= 0) return PW_OK;
     for (int pass = 0; pass < 2; ++pass) {
       GramArgs g;
       g.A = V; g.a_kstride = (long)nbmax * npwx; g.a_off = d_nb; g.a_cnt = d_nnc;
-      g.B = V; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = d_nnc;
+      g.B = SV; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = d_nnc;
       g.ld = npwx; g.npw = c->d_npw;
       g.C = Sm; g.c_kstride = (long)nbnd * nbnd; g.ldc = nbnd;
       TRY(launch_gram(c, g, nnc_max, nnc_max, st));
       TRY(launch_chol_inv(c, Sm, (long)nbnd * nbnd, nbnd, d_nnc, Mm, (long)nbnd * nbnd, nbnd, d_info, st));
       TRY(launch_trmm(c, V, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
+      if (gen) TRY(launch_trmm(c, SV, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
       HIPTRY(c, hipMemcpyAsync(info.data(), d_info, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
       HIPTRY(c, sync());
       bool changed = false;
@@ -373,6 +419,7 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
         hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(256), 0, st, Rb, nbnd, V, nbmax, d_nb, d_nnc, d_map, npwx,
                            d_mask);
         TRY(check_launch(c, "gather_r", st));
+        TRY(apply_s(nnc_max));
         TRY(project(nb_max, nnc_max));
       }
     }
@@ -414,6 +461,16 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
       m.ld = npwx; m.Cm = Cr; m.c_kstride = (long)nbmax * nbnd; m.ldc = nbnd;
       TRY(launch_combine(c, m, nb_max, st));
     }
+    if (gen) {
+      // S X afresh rather than SV C: the S-images carried along with the basis
+      // drift by rounding over the row updates, and the residuals, the next
+      // restart and the final S-orthonormality all read SX
+      VecSel sel;
+      sel.nvec = nbnd;
+      sel.kstride = (long)nbnd * npwx;
+      sel.cnt = d_ny;
+      TRY(launch_spsi(c, PW_FP64, sel, X, SX, nullptr, 0.0, st));
+    }
     return PW_OK;
   };
 
@@ -426,9 +483,12 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     std::fill(nnc.begin(), nnc.end(), nbnd);
     HIPTRY(c, h2d(d_nb, nb));
     HIPTRY(c, h2d(d_nnc, nnc));
+    TRY(apply_s(nbnd));
     TRY(orthonormalize(0, nbnd, false));
     for (int k = 0; k < nk; ++k)
-      if (nnc[k] == 0) return set_err(c, PW_EINVAL, "starting vectors are linearly dependent at k " + std::to_string(k));
+      if (nnc[k] == 0) return set_err(c, PW_EINVAL,
+                       std::string("starting vectors are linearly dependent") +
+                           (gen ? " (or S is not positive definite)" : "") + " at k " + std::to_string(k));
     TRY(apply_h(nbnd));
     HIPTRY(c, hipMemsetAsync(Hr, 0, sizeof(cd) * (size_t)nk * nbmax * nbmax, st));
     TRY(extend_h(nbnd, nbnd));
@@ -444,8 +504,8 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     HIPTRY(c, h2d(d_active, active));
     {
       dim3 grid(nbnd, nk);
-      hipLaunchKernelGGL(resid_kernel, grid, dim3(256), 0, st, X, HX, theta, d_active, hd, c->d_npw, npwx, nbnd, T,
-                         Rb, rn);
+      hipLaunchKernelGGL(resid_kernel, grid, dim3(256), 0, st, SX, HX, theta, d_active, hd, sd, c->d_npw, npwx, nbnd,
+                         T, Rb, rn);
       TRY(check_launch(c, "resid", st));
     }
     HIPTRY(c, hipMemcpyAsync(th.data(), theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
@@ -491,6 +551,10 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
         dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
         hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, X, nbnd, V, nbmax, nbnd, npwx);
         TRY(check_launch(c, "copy", st));
+        if (gen) {
+          hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, SX, nbnd, SV, nbmax, nbnd, npwx);
+          TRY(check_launch(c, "copy", st));
+        }
         std::fill(nb.begin(), nb.end(), 0);
         std::fill(nnc.begin(), nnc.end(), nbnd);
         HIPTRY(c, h2d(d_nb, nb));
@@ -510,7 +574,8 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     HIPTRY(c, h2d(d_nnc, nnc));
     {
       dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
-      hipLaunchKernelGGL(restart_kernel, grid, dim3(256), 0, st, d_flag, X, HX, V, HV, nbnd, nbmax, npwx, Hr, theta);
+      hipLaunchKernelGGL(restart_kernel, grid, dim3(256), 0, st, d_flag, X, HX, gen ? SX : nullptr, V, HV, SV, nbnd,
+                         nbmax, npwx, Hr, theta);
       TRY(check_launch(c, "restart", st));
     }
     HIPTRY(c, h2d(d_nb, nb));
@@ -520,6 +585,7 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
                          (const int*)nullptr);
       TRY(check_launch(c, "gather", st));
     }
+    TRY(apply_s(nnc_max));
     int nb_cur_max = 0;
     for (int k = 0; k < nk; ++k) nb_cur_max = std::max(nb_cur_max, nb[k]);
     TRY(orthonormalize(nb_cur_max, nnc_max, true));

@@ -147,6 +147,10 @@ struct pw_ctx {
   void* d_dij64 = nullptr;   // (nproj, nproj) complex double
   void* d_dij32 = nullptr;
   std::vector<double> dij;   // host copy, complex interleaved
+  bool have_q = false;       // overlap S = 1 + sum_pq |beta_p> q_pq <beta_q| set
+  void* d_q64 = nullptr;     // (nproj, nproj) complex double
+  void* d_q32 = nullptr;     // complex float
+  std::vector<double> qij;   // host copy, complex interleaved
 
   mkpw::KTables tables() const;
 };
@@ -163,6 +167,14 @@ pw_status launch_hpsi(pw_ctx* c, pw_prec prec, const VecSel& sel, const void* ps
                       hipStream_t stream);
 bool hpsi_supported(int n1, int n2, int n3);
 
+// S|psi> = psi + sum_pq beta_p q_pq <beta_q|psi> over the selected vectors
+// (spsi.hip; S = 1 when no overlap is set).  Without `scale` it writes
+// out = S psi (padding zero); with `scale` ([nk * sel.nvec], indexed by k and
+// the row's position in the selection) it accumulates
+// out += mult * scale[k * sel.nvec + r] * S psi on the plane waves of k.
+pw_status launch_spsi(pw_ctx* c, pw_prec prec, const VecSel& sel, const void* psi, void* out, const double* scale,
+                      double mult, hipStream_t st);
+
 pw_status check_launch(pw_ctx* c, const char* what, hipStream_t st);
 // thread-safe, once-per-kernel raise of the dynamic LDS limit (needed above 64 KiB)
 pw_status ensure_lds_limit(pw_ctx* c, const void* kernel, size_t lds);
@@ -175,7 +187,8 @@ pw_status launch_to_c64(pw_ctx* c, const cplx<double>* src, long s_kstride, cons
 pw_status launch_to_c128(pw_ctx* c, const cplx<float>* src, long s_kstride, const int* s_off, cplx<double>* dst,
                          long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st);
 
-// Hermitian eigensolver (cyclic parallel Jacobi, one workgroup per k, LDS):
+// Hermitian eigensolver (Householder tridiagonalization, bisection and inverse
+// iteration, one workgroup per k, LDS):
 // for each k with n[k] > 0, the n x n matrix A(k) (lda-strided) -> the lowest
 // nev eigenvalues (ascending) into w[k*nev..] and their eigenvectors as the
 // columns of V(k) (n x nev, ldv-strided).  n <= 64.

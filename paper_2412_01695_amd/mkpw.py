@@ -26,8 +26,8 @@ STATUS_NAMES = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EDEVICE", 
                 -5: "PW_ESTATE"}
 
 EXPORTS = ["pw_create", "pw_destroy", "pw_last_error", "pw_set_option", "pw_get_option", "pw_set_lattice", "pw_set_cutoff",
-           "pw_set_kpoints", "pw_get_miller", "pw_set_vloc", "pw_set_projectors", "pw_init_guess", "pw_h_psi",
-           "pw_davidson", "pw_dfpt_cg"]
+           "pw_set_kpoints", "pw_get_miller", "pw_set_vloc", "pw_set_projectors", "pw_set_qij", "pw_init_guess",
+           "pw_h_psi", "pw_s_psi", "pw_davidson", "pw_dfpt_cg"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2412_01695_amd.build`")
@@ -57,8 +57,10 @@ _sig = {
     "pw_get_miller": (_i, [_vp, _i, _pi]),
     "pw_set_vloc": (_i, [_vp, _pd]),
     "pw_set_projectors": (_i, [_vp, _i, _vp, _vp]),
+    "pw_set_qij": (_i, [_vp, _vp]),
     "pw_init_guess": (_i, [_vp, _i, C.c_uint64, _vp]),
     "pw_h_psi": (_i, [_vp, _i, _i, _vp, _vp]),
+    "pw_s_psi": (_i, [_vp, _i, _i, _vp, _vp]),
     "pw_davidson": (_i, [_vp, _i, _i, _vp, _pd, _d, _i, _pi, _pi]),
     "pw_dfpt_cg": (_i, [_vp, _i, _i, _vp, _pd, _pd, _i, _vp, _vp, _d, _i, _pi]),
 }
@@ -180,8 +182,20 @@ def pw_set_projectors(ctx, beta, dij):
                                               dij.ctypes.data if nproj else None))
 
 
+def pw_set_qij(ctx, qij):
+    """qij: host complex128 (nproj, nproj), or None to remove the overlap."""
+    if qij is None:
+        return _check(ctx, _lib.pw_set_qij(ctx, None))
+    q = np.ascontiguousarray(qij, dtype=np.complex128)
+    return _check(ctx, _lib.pw_set_qij(ctx, q.ctypes.data))
+
+
 def pw_h_psi(ctx, prec: int, nbnd: int, psi, hpsi):
     return _check(ctx, _lib.pw_h_psi(ctx, int(prec), int(nbnd), _ptr(psi), _ptr(hpsi)))
+
+
+def pw_s_psi(ctx, prec: int, nbnd: int, psi, spsi):
+    return _check(ctx, _lib.pw_s_psi(ctx, int(prec), int(nbnd), _ptr(psi), _ptr(spsi)))
 
 
 def pw_davidson(ctx, prec: int, nbnd: int, psi, nk: int, tol_ry: float, max_iter: int):

@@ -2,8 +2,9 @@
 
 ``System(cfg)`` creates a ``pw_ctx`` for one ``synth.Config``: lattice,
 cutoff and FFT mesh, the k-point list (the library builds the bases), the
-local potential on the mesh, and the projector values at every k+G of the
-library's own plane-wave order.  It also lays out wavefunction arrays in
+local potential on the mesh, the projector values at every k+G of the
+library's own plane-wave order and, when the config has them, the overlap
+coefficients q.  It also lays out wavefunction arrays in
 the library's (nk, nvec, npwx) format.
 """
 from __future__ import annotations
@@ -52,6 +53,8 @@ class System:
                     o += n
                 self.beta = beta
                 mkpw.pw_set_projectors(self.ctx, beta, cfg.dij if dij is None else dij)
+                if cfg.qij is not None:
+                    mkpw.pw_set_qij(self.ctx, cfg.qij)
         except Exception:
             mkpw.pw_destroy(self.ctx)
             self.ctx = None

@@ -32,6 +32,7 @@ def _run(torch, sysm, psi, prec):
     dt = torch.complex128 if prec == mkpw.PW_FP64 else torch.complex64
     d_psi = to_dev(torch, psi, dt)
     d_h = torch.full_like(d_psi, float("nan"))
+    torch.cuda.synchronize()  # torch's fill runs on its own stream, the library on the context's
     mkpw.pw_h_psi(sysm.ctx, prec, psi.shape[1], d_psi, d_h)
     torch.cuda.synchronize()
     return d_h.cpu().numpy().astype(np.complex128)
@@ -232,6 +233,7 @@ def test_device_initial_guess_matches_generator():
     cfg = synth.subset(synth.make_config(2), np.arange(0, 512, 9))
     torch, s = _system(cfg)
     d = torch.full((cfg.nk, cfg.nbnd, s.npwx), float("nan"), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
     mkpw.pw_init_guess(s.ctx, cfg.nbnd, cfg.seed, d)
     torch.cuda.synchronize()
     ref = synth.psi_guess_all(cfg, s.miller, s.npwx)

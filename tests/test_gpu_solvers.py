@@ -48,6 +48,7 @@ def _davidson(torch, s, prec, tol_ry, max_iter=300, nbnd=None):
 def _check_vectors(torch, s, psi, eig, tol_res):
     from paper_2412_01695_amd import mkpw
     h = torch.empty_like(psi)
+    torch.cuda.synchronize()
     mkpw.pw_h_psi(s.ctx, mkpw.PW_FP64, eig.shape[1], psi, h)
     torch.cuda.synchronize()
     p = psi.cpu().numpy()
@@ -182,6 +183,7 @@ def _run_cg(torch, s, prec, u, rhs, eps, alpha, thr=THR, max_iter=1000):
     du = to_dev(torch, u)
     drhs = to_dev(torch, rhs)
     dx = torch.zeros_like(drhs)
+    torch.cuda.synchronize()  # torch's fill runs on its own stream, the library on the context's
     st, iters = mkpw.pw_dfpt_cg(s.ctx, prec, u.shape[1], du, eps, alpha, rhs.shape[1], drhs, dx, thr, max_iter)
     torch.cuda.synchronize()
     return st, iters, dx.cpu().numpy()

@@ -111,6 +111,48 @@ def test_error_paths(mk):
     mk.pw_destroy(ctx)
 
 
+def test_overlap_coefficients(mk):
+    # q needs projectors first, must be Hermitian, and goes away with new projectors or NULL
+    cfg = synth.make_config(1)
+    ctx = _host_ctx(mk, cfg)
+    try:
+        npw, npwx = mk.pw_set_kpoints(ctx, cfg.kpts)
+        q = synth.q_model(cfg)
+        with pytest.raises(mk.PwError) as e:
+            mk.pw_set_qij(ctx, q)
+        assert e.value.status == mk.PW_ESTATE
+        beta = np.zeros((cfg.nk, cfg.nproj, npwx), dtype=np.complex128)
+        mk.pw_set_projectors(ctx, beta, cfg.dij)
+        assert mk.pw_get_option(ctx, "overlap") == 0
+        bad = q.copy()
+        bad[0, 1] = 0.2 + 0.1j
+        with pytest.raises(mk.PwError) as e:
+            mk.pw_set_qij(ctx, bad)
+        assert e.value.status == mk.PW_EINVAL and "Hermitian" in str(e.value)
+        bad = q.copy()
+        bad[2, 2] = np.inf
+        with pytest.raises(mk.PwError) as e:
+            mk.pw_set_qij(ctx, bad)
+        assert e.value.status == mk.PW_EINVAL
+        herm = q.copy()
+        herm[0, 1], herm[1, 0] = 0.2 + 0.1j, 0.2 - 0.1j
+        mk.pw_set_qij(ctx, herm)
+        assert mk.pw_get_option(ctx, "overlap") == 1
+        mk.pw_set_qij(ctx, None)
+        assert mk.pw_get_option(ctx, "overlap") == 0
+        mk.pw_set_qij(ctx, q)
+        mk.pw_set_projectors(ctx, beta, cfg.dij)     # new projectors drop q
+        assert mk.pw_get_option(ctx, "overlap") == 0
+        mk.pw_set_qij(ctx, q)
+        mk.pw_set_kpoints(ctx, cfg.kpts)              # so do new k-points
+        assert mk.pw_get_option(ctx, "overlap") == 0
+        with pytest.raises(mk.PwError) as e:
+            mk.pw_s_psi(ctx, mk.PW_FP64, 4, 0, 0)
+        assert e.value.status == mk.PW_ESTATE
+    finally:
+        mk.pw_destroy(ctx)
+
+
 def test_shape_options(mk):
     # the H|psi> launch-shape options: accepted values round-trip, others are refused
     ctx = mk.pw_create(-1, None)
