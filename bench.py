@@ -136,6 +136,8 @@ def cpu_baseline(cfg, vloc, miller_by_k, min_seconds=10.0, max_rounds=3):
 
 def oracle_eig_error(cfg, vloc, miller_lib, eigs, nsample=8):
     """max |eig - dense eig| (Ry) on sampled k-points, per solve in `eigs`."""
+    import scipy.linalg
+
     from oracle import hamiltonian as ham
     from paper_2412_01695_amd import synth
 
@@ -146,7 +148,11 @@ def oracle_eig_error(cfg, vloc, miller_lib, eigs, nsample=8):
     ks = np.unique(np.linspace(0, cfg.nk - 1, nsample).astype(int))
     err = {name: 0.0 for name in eigs}
     for ik in ks:
-        ref = np.linalg.eigvalsh(ham.KPoint(cfg, int(ik), vt, bfn).h)[:cfg.nbnd]
+        kp = ham.KPoint(cfg, int(ik), vt, bfn)
+        if cfg.qij is None:
+            ref = np.linalg.eigvalsh(kp.h)[:cfg.nbnd]
+        else:
+            ref = scipy.linalg.eigh(kp.h, kp.s, eigvals_only=True)[:cfg.nbnd]
         for name, e in eigs.items():
             err[name] = max(err[name], float(np.max(np.abs(e[ik] - ref))) * 2.0)
     return err, [int(k) for k in ks]
@@ -220,6 +226,61 @@ def dfpt_sample(torch, mkpw, cfg_id, thr=1e-24):
         sysm.close()
 
 
+def time_spsi(torch, mkpw, ctx, prec, nbnd, psi, spsi, steps, warmup):
+    for _ in range(warmup):
+        mkpw.pw_s_psi(ctx, prec, nbnd, psi, spsi)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()   # the context's stream (set by the caller)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        mkpw.pw_s_psi(ctx, prec, nbnd, psi, spsi)
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def overlap_sample(torch, mkpw, cfg_id, steps, warmup, solve, check):
+    """The workload with the model overlap S = 1 + beta q beta^H: one pw_s_psi
+    over the whole batch timed like H|psi> (HBM-bound: psi in, S psi out, the
+    projector rows of each k shared by its bands), and the generalized
+    Davidson (H psi = eps S psi) to 1e-10 Ry in FP64 and to 1e-6 Ry mixed."""
+    from paper_2412_01695_amd import synth
+    from paper_2412_01695_amd.system import System
+
+    cfg = synth.with_overlap(synth.make_config(cfg_id))
+    sysm = System(cfg, 0)
+    torch.cuda.set_stream(sysm.stream)
+    try:
+        nbnd, nkb = cfg.nbnd, cfg.nk * cfg.nbnd
+        psi = torch.from_numpy(sysm.psi_guess()).cuda()
+        sp = torch.empty_like(psi)
+        ms = time_spsi(torch, mkpw, sysm.ctx, mkpw.PW_FP64, nbnd, psi, sp, steps, warmup)
+        npw = sysm.npw.astype(np.float64)
+        io = float(np.sum(2.0 * 16.0 * npw * nbnd + 16.0 * cfg.nproj * npw))
+        gbs = io / (ms * 1e-3) / 1e9
+        out = {"workload": f"{cfg.name}: {cfg.nk} k x {nbnd} bands, {cfg.nproj} projectors, q per atom "
+                           f"s 16 / p 12 (two channels coupled 4 / 3)",
+               "s_psi": {"ms_per_call": ms, "kband_per_s": nkb / (ms * 1e-3), "dtype": "c128",
+                         "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                      "frac": gbs / PEAK_HBM_GBS, "kernel": "spsi_kernel",
+                                      "bytes_per_launch": io}}}
+        eigs = {}
+        for name, prec, tol in (("fp64", mkpw.PW_FP64, 1e-10), ("mixed", mkpw.PW_MIXED, 1e-6)):
+            if not solve:
+                break
+            out[name], eigs[name] = time_davidson(torch, mkpw, sysm, prec, tol)
+            out[name]["kband_per_s"] = nkb / out[name]["seconds"]
+        if check and eigs:
+            err, ks = oracle_eig_error(cfg, sysm.vloc, sysm.miller, eigs)
+            for name in eigs:
+                out[name]["max_eig_err_vs_oracle_ry"] = err[name]
+            out["oracle_k_sample"] = ks
+        return out
+    finally:
+        sysm.close()
+
+
 def serving_sample(n, rate=20.0):
     from paper_2412_01695_amd import serve
     reqs = serve.make_requests(n, rate)
@@ -261,6 +322,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--dfpt-config", type=int, default=3, help="workload of the DFPT CG sample (0: skip)")
+    ap.add_argument("--overlap-config", type=int, default=2,
+                    help="workload of the overlap (S psi, generalized Davidson) sample (0: skip)")
     ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--shape", default=None,
                     help="fix the H|psi> launch shape as variant,threads,slab (e.g. 1,256,10) instead of "
@@ -380,6 +443,9 @@ def main():
                 res["solve"][name]["max_eig_err_vs_oracle_ry"] = err[name]
             res["solve"]["oracle_k_sample"] = ks
     sysm.close()
+    if args.overlap_config > 0:
+        res["overlap"] = overlap_sample(torch, mkpw, args.overlap_config, args.steps, args.warmup,
+                                        not args.no_solve, not args.no_cpu)
     if args.dfpt_config > 0:
         res["dfpt"] = dfpt_sample(torch, mkpw, args.dfpt_config)
     if args.serve_requests > 0:
