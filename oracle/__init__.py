@@ -19,6 +19,9 @@ Modules
                (Sec. 2.1, with S), the paper's preconditioned CG (Sec. 2.4)
                and the closed-form solution of the DFPT linear system
                (Sec. 2.3, with S)
+  response     the perturbation from the k to the k+q sphere (dense and
+               through the mesh), the right-hand side at q != 0 and the
+               induced density of Eq. drho
 
 Parity status: every function here is pinned by the CPU tests in
 tests/test_oracle_*.py against closed forms, invariants, brute force or

@@ -148,6 +148,37 @@ def with_overlap(cfg: Config, qij=None) -> Config:
     return c
 
 
+def q_paper() -> np.ndarray:
+    """The phonon wavevector of the paper's benchmark, (2 pi / a)(-1/8, -1/4, 3/8), here
+    in units of this cell's a (Cartesian bohr^-1)."""
+    return (2.0 * math.pi / A_FCC) * np.array([-0.125, -0.25, 0.375])
+
+
+def shifted(cfg: Config, q_cart) -> Config:
+    """The same workload with every k-point moved by q (the k+q list of a response
+    calculation at wavevector q)."""
+    c = Config(cfg.name + "-kq", cfg.lat, cfg.ecut_ry, cfg.fft, cfg.kpts + np.asarray(q_cart)[None, :],
+               cfg.nbnd, cfg.tau, cfg.projectors, cfg.dij, cfg.seed, dict(cfg.extra), cfg.qij)
+    return c
+
+
+def dv_complex_grid(cfg: Config, seed: int = 11) -> np.ndarray:
+    """A complex lattice-periodic perturbation (the periodic part of a potential at
+    q != 0 need not be real): sum over 0 < |G|^2 <= 4 (2 pi/a)^2 of
+    c_G exp(iG.r) / (1 + |G|^2), c_G = exp(i phi_G), phi ~ U[0, 2 pi) from `seed`."""
+    g2max = 4.0 * (2.0 * math.pi / A_FCC) ** 2
+    m, g = _lattice_vectors_in_sphere(cfg.lat, g2max)
+    keep = np.any(m != 0, axis=1)
+    m, g = m[keep], g[keep]
+    phi = np.random.default_rng(seed).uniform(0.0, 2.0 * math.pi, size=m.shape[0])
+    amp = 1.0 / (1.0 + np.einsum("ij,ij->i", g, g))
+    fr = _grid_frac(cfg.fft)
+    out = np.zeros(fr.shape[0], dtype=np.complex128)
+    for j in range(m.shape[0]):
+        out += amp[j] * np.exp(1j * (phi[j] + 2.0 * math.pi * (fr @ m[j])))
+    return out.reshape(cfg.fft)
+
+
 def make_config(cid: int) -> Config:
     """The four batch workloads (ids 1..4); id 5 is the serving stream (`serving_requests`)."""
     lat = fcc_lattice()

@@ -3,17 +3,19 @@
 Each case patches one plausible slip into the oracle (a flipped sign, a
 transposed index, a dropped conjugate, a missing normalisation, a wrong
 kinetic factor, a wrong CG step, a transposed or unconjugated overlap term,
-the overlap left out of a residual or a projector) and checks that at least one pin test
+the overlap left out of a residual or a projector, a reversed perturbation index, the
+conjugate on the wrong factor of the induced density, a missing factor 4) and checks that at least one pin test
 then fails."""
 import numpy as np
 import pytest
 
-from oracle import basis, dft, hamiltonian as ham, solvers
+from oracle import basis, dft, hamiltonian as ham, response, solvers
 from paper_2412_01695_amd import synth
 
 import test_oracle_dft as tdft
 import test_oracle_hamiltonian as tham
 import test_oracle_overlap as tovl
+import test_oracle_response as tresp
 import test_oracle_solvers as tsol
 
 
@@ -110,3 +112,30 @@ def _c1s():
     v = synth.vloc_grid(cfg)
     vt = ham.vtilde(v)
     return cfg, v, [ham.KPoint(cfg, ik, vt, tovl.beta_fn) for ik in range(cfg.nk)]
+
+
+def test_reversed_perturbation_index_is_caught(monkeypatch):
+    orig = response.dv_cross_matrix
+    monkeypatch.setattr(response, "dv_cross_matrix", lambda mo, mi, fft, dvt: orig(mi, mo, fft, dvt).T)
+    assert _fails(tresp.test_single_fourier_component_perturbation, _c1q())
+
+
+def test_drho_conjugate_on_the_wrong_factor_is_caught(monkeypatch):
+    def bad(fft, weights, miller_k, u_k, miller_kq, du_kq):
+        out = np.zeros(tuple(fft), dtype=np.complex128)
+        for w, mk, uk, mq, dq in zip(weights, miller_k, u_k, miller_kq, du_kq):
+            out += 4.0 * w * np.sum(response.to_mesh(mk, fft, uk) * response.to_mesh(mq, fft, dq).conj(), axis=0)
+        return out
+    monkeypatch.setattr(response, "drho", bad)
+    assert _fails(tresp.test_drho_of_two_plane_waves)
+
+
+def test_drho_without_the_factor_four_is_caught(monkeypatch):
+    orig = response.drho
+    monkeypatch.setattr(response, "drho", lambda *a: 0.25 * orig(*a))
+    assert _fails(tresp.test_drho_at_q0_is_a_density)
+
+
+def _c1q():
+    cfg = synth.make_config(1)
+    return cfg, synth.shifted(cfg, synth.q_paper())
