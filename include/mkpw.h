@@ -190,6 +190,37 @@ pw_status pw_dfpt_cg(pw_ctx* ctx, pw_prec prec, int nocc, const void* psi_occ, c
                const double* alpha_ha, int nrhs, const void* rhs, void* dpsi, double thr, int max_iter,
                int32_t* iters);
 
+/* Right-hand sides of the DFPT linear systems at a wavevector q (Sec. 2.3,
+ * Eq. linear_system with dS = 0; Algorithm phonon_new, "build P_c dV u"):
+ *   rhs_{k,nu} = -(1 - S P_v^{k+q}) dV u_{k,nu},
+ *   (dV u)(G') = sum_G dV~[(m_G' - m_G) mod N] u(G),  G on the k sphere,
+ *   G' on the k+q sphere, dV~ the forward transform of dV(r) with 1/N_r.
+ * ctx_kq holds the k+q list (k-point i = k_i + q), ctx_k the k list, on the
+ * same device, lattice and mesh with the same number of k-points (else
+ * PW_EINVAL); work runs on ctx_kq's stream (ctx_k must have no pending work).
+ * dv_r: host complex128 N1*N2*N3 (C order), the lattice-periodic part of the
+ * perturbing potential in Ha.  psi_k: device complex128 (nk, nocc, npwx_k),
+ * the occupied states at k.  psi_occ_kq: device complex128 (nk, nocc,
+ * npwx_kq), the S-orthonormal occupied states at k+q (S of ctx_kq).
+ * rhs: device complex128 (nk, nocc, npwx_kq), written (padding zero); feed it
+ * to pw_dfpt_cg on ctx_kq with psi_occ_kq and the eigenvalues at k.
+ * 1 <= nocc <= 64.  FP64. */
+pw_status pw_dfpt_rhs(pw_ctx* ctx_kq, const pw_ctx* ctx_k, int nocc, const void* dv_r, const void* psi_k,
+                const void* psi_occ_kq, void* rhs);
+
+/* Density induced by a perturbation at q (Sec. 2.3, Eq. drho without the
+ * augmentation term):  drho(r_l) = 4 sum_k w_k sum_nu conj(u_{k,nu}(r_l))
+ * du_{k,nu}(r_l), with u(r_l) = sum_G u(G) exp(2 pi i m_G . l / N) (the
+ * inverse transform of Sec. 4, no normalisation).  Contexts as for
+ * pw_dfpt_rhs.  wk: host (nk) k-point weights.  psi_k: device complex128
+ * (nk, nbnd, npwx_k).  dpsi_kq: device complex128 (nk, nbnd, npwx_kq), the
+ * solutions of pw_dfpt_cg (in the conduction manifold).  drho_r: device
+ * complex128 N1*N2*N3 (C order), written.  1 <= nbnd <= 1024.  FP64.
+ * PW_EINVAL if the spheres are too large for the difference bins held in LDS
+ * (more than about 9000 distinct Miller differences per x-plane). */
+pw_status pw_drho(pw_ctx* ctx_kq, const pw_ctx* ctx_k, int nbnd, const double* wk, const void* psi_k,
+            const void* dpsi_kq, void* drho_r);
+
 #ifdef __cplusplus
 }
 #endif

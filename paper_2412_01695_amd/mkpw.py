@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EDEVICE", 
 
 EXPORTS = ["pw_create", "pw_destroy", "pw_last_error", "pw_set_option", "pw_get_option", "pw_set_lattice", "pw_set_cutoff",
            "pw_set_kpoints", "pw_get_miller", "pw_set_vloc", "pw_set_projectors", "pw_set_qij", "pw_init_guess",
-           "pw_h_psi", "pw_s_psi", "pw_davidson", "pw_dfpt_cg"]
+           "pw_h_psi", "pw_s_psi", "pw_davidson", "pw_dfpt_cg", "pw_dfpt_rhs", "pw_drho"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2412_01695_amd.build`")
@@ -63,6 +63,8 @@ _sig = {
     "pw_s_psi": (_i, [_vp, _i, _i, _vp, _vp]),
     "pw_davidson": (_i, [_vp, _i, _i, _vp, _pd, _d, _i, _pi, _pi]),
     "pw_dfpt_cg": (_i, [_vp, _i, _i, _vp, _pd, _pd, _i, _vp, _vp, _d, _i, _pi]),
+    "pw_dfpt_rhs": (_i, [_vp, _vp, _i, _vp, _vp, _vp, _vp]),
+    "pw_drho": (_i, [_vp, _vp, _i, _pd, _vp, _vp, _vp]),
 }
 for _n, (_r, _a) in _sig.items():
     _f = getattr(_lib, _n)
@@ -219,3 +221,15 @@ def pw_dfpt_cg(ctx, prec: int, nocc: int, psi_occ, eps_ha, alpha_ha, nrhs: int, 
                          float(thr), int(max_iter), iters.ctypes.data_as(_pi))
     _check(ctx, st, allow_noconv=True)
     return st, iters
+
+
+def pw_dfpt_rhs(ctx_kq, ctx_k, nocc: int, dv_r, psi_k, psi_occ_kq, rhs):
+    """dv_r: host complex (N1, N2, N3); device arrays as torch tensors or pointers."""
+    dv = np.ascontiguousarray(dv_r, dtype=np.complex128)
+    return _check(ctx_kq, _lib.pw_dfpt_rhs(ctx_kq, ctx_k, int(nocc), dv.ctypes.data, _ptr(psi_k), _ptr(psi_occ_kq),
+                                           _ptr(rhs)))
+
+
+def pw_drho(ctx_kq, ctx_k, nbnd: int, wk, psi_k, dpsi_kq, drho_r):
+    w, pw = _dbl(wk)
+    return _check(ctx_kq, _lib.pw_drho(ctx_kq, ctx_k, int(nbnd), pw, _ptr(psi_k), _ptr(dpsi_kq), _ptr(drho_r)))

@@ -1,0 +1,159 @@
+"""Linear response at q != 0 through the C-ABI on the GPU, against the FP64 oracle.
+
+pw_dfpt_rhs: -(1 - S P_v^{k+q}) dV u_k element by element within 1e-12 of the
+largest element of the oracle's dense result (the direct sum over the pairs of
+the two spheres and the oracle's matrix product differ only in rounding order).
+pw_drho: the induced density on the mesh within 1e-12 of its largest value
+against the oracle's literal Eq. drho (both bands' real-space values from the
+oracle's DFT).  End to end at the paper's q: Davidson at k and k+q, the
+right-hand side, the CG at k+q and the density, against the oracle's exact
+solves with the library's own eigenvectors, within 1e-9."""
+import numpy as np
+import pytest
+
+from oracle import dft, hamiltonian as ham, response, solvers
+from paper_2412_01695_amd import synth
+
+from gpu_util import to_dev, torch_cuda
+from helpers import beta_fn, miller_map
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(cfg, q):
+    torch = torch_cuda()
+    from paper_2412_01695_amd.system import System
+    sk = System(cfg, 0)
+    sq = System(synth.shifted(cfg, q), 0)
+    return torch, sk, sq
+
+
+def _to_oracle(s, ik, rows, kp):
+    """(nb, npwx) library rows of k-point ik -> (nb, npw) in the oracle's order."""
+    perm = miller_map(s.miller[ik], kp.miller)
+    out = np.zeros((rows.shape[0], kp.npw), complex)
+    out[:, perm] = rows[:, :s.npw[ik]]
+    return out
+
+
+def _to_lib(s, ik, rows, kp):
+    perm = miller_map(s.miller[ik], kp.miller)
+    out = np.zeros((rows.shape[0], s.npwx), complex)
+    out[:, :s.npw[ik]] = rows[:, perm]
+    return out
+
+
+@pytest.mark.parametrize("cid,step,overlap", [(1, 1, False), (1, 1, True), (3, 256, True)])
+def test_dfpt_rhs_matches_oracle(cid, step, overlap):
+    from paper_2412_01695_amd import mkpw
+    cfg0 = synth.make_config(cid)
+    cfg = synth.subset(cfg0, np.arange(0, cfg0.nk, step))
+    if overlap:
+        cfg = synth.with_overlap(cfg)
+    torch, sk, sq = _pair(cfg, synth.q_paper())
+    nocc = 5
+    dv = synth.dv_complex_grid(cfg)
+    dvt = dft.forward(dv)
+    vt = ham.vtilde(sk.vloc)
+    u_k = sk.psi_guess(nocc)
+    u_q = np.zeros((cfg.nk, nocc, sq.npwx), complex)
+    ref = np.zeros((cfg.nk, nocc, sq.npwx), complex)
+    for ik in range(cfg.nk):
+        kk = ham.KPoint(cfg, ik, vt, beta_fn)
+        kq = ham.KPoint(sq.cfg, ik, vt, beta_fn)
+        _, uq = solvers.lowest_eigpairs(kq.h, nocc, kq.s if overlap else None)
+        u_q[ik] = _to_lib(sq, ik, uq.T, kq)
+        dvu = response.dv_cross_matrix(kq.miller, kk.miller, cfg.fft, dvt) @ _to_oracle(sk, ik, u_k[ik], kk).T
+        r = response.dfpt_rhs_q(dvu, uq, kq.s if overlap else None)
+        ref[ik] = _to_lib(sq, ik, r.T, kq)
+    d_rhs = torch.full((cfg.nk, nocc, sq.npwx), float("nan"), dtype=torch.complex128, device="cuda")
+    d_uk, d_uq = to_dev(torch, u_k), to_dev(torch, u_q)
+    torch.cuda.synchronize()
+    mkpw.pw_dfpt_rhs(sq.ctx, sk.ctx, nocc, dv, d_uk, d_uq, d_rhs)
+    torch.cuda.synchronize()
+    got = d_rhs.cpu().numpy()
+    err = np.max(np.abs(got - ref))
+    print(cfg.name, "overlap", overlap, "rhs rel err", err / np.max(np.abs(ref)))
+    assert err <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("cid,step", [(1, 1), (3, 256)])
+def test_drho_matches_oracle(cid, step):
+    from paper_2412_01695_amd import mkpw
+    cfg0 = synth.make_config(cid)
+    cfg = synth.subset(cfg0, np.arange(0, cfg0.nk, step))
+    torch, sk, sq = _pair(cfg, synth.q_paper())
+    nb = 6
+    u_k = sk.psi_guess(nb)
+    du = np.zeros((cfg.nk, nb, sq.npwx), complex)
+    for ik in range(cfg.nk):
+        du[ik, :, :sq.npw[ik]] = synth.random_vectors(9, ik, sq.miller[ik], nb)
+    w = np.linspace(0.5, 1.5, cfg.nk) / cfg.nk
+    ref = response.drho(cfg.fft, w, sk.miller, [u_k[ik, :, :sk.npw[ik]] for ik in range(cfg.nk)],
+                        sq.miller, [du[ik, :, :sq.npw[ik]] for ik in range(cfg.nk)])
+    d_out = torch.full(cfg.fft, float("nan"), dtype=torch.complex128, device="cuda")
+    d_uk, d_du = to_dev(torch, u_k), to_dev(torch, du)
+    torch.cuda.synchronize()
+    mkpw.pw_drho(sq.ctx, sk.ctx, nb, w, d_uk, d_du, d_out)
+    torch.cuda.synchronize()
+    got = d_out.cpu().numpy()
+    err = np.max(np.abs(got - ref))
+    print(cfg.name, "drho rel err", err / np.max(np.abs(ref)))
+    assert err <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_dfpt_at_q_end_to_end():
+    # the paper's q on the 4-k cell: one occupied band (a gap to the rest at every k and k+q)
+    from paper_2412_01695_amd import mkpw
+    cfg = synth.with_overlap(synth.make_config(1))
+    q = synth.q_paper()
+    torch, sk, sq = _pair(cfg, q)
+    nocc, nb = 1, 4
+    vt = ham.vtilde(sk.vloc)
+    uk = to_dev(torch, sk.psi_guess(nb))
+    uq = to_dev(torch, sq.psi_guess(nb))
+    st, ek, _, _ = mkpw.pw_davidson(sk.ctx, 0, nb, uk, cfg.nk, 1e-12, 300)
+    assert st == 0
+    st, eq, _, _ = mkpw.pw_davidson(sq.ctx, 0, nb, uq, cfg.nk, 1e-12, 300)
+    assert st == 0
+    torch.cuda.synchronize()
+    assert np.min(eq[:, nocc]) > np.max(ek[:, nocc - 1]) + 0.1
+    uk_o = uk[:, :nocc].contiguous()
+    uq_o = uq[:, :nocc].contiguous()
+    dv = synth.dv_complex_grid(cfg)
+    rhs = torch.zeros((cfg.nk, nocc, sq.npwx), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    mkpw.pw_dfpt_rhs(sq.ctx, sk.ctx, nocc, dv, uk_o, uq_o, rhs)
+    eps = np.ascontiguousarray(ek[:, :nocc])
+    alpha = np.maximum(2.0 * (np.maximum(ek[:, nocc - 1], eq[:, nocc - 1]) - np.minimum(ek[:, 0], eq[:, 0])), 0.1)
+    x = torch.zeros_like(rhs)
+    torch.cuda.synchronize()
+    st, iters = mkpw.pw_dfpt_cg(sq.ctx, 0, nocc, uq_o, eps, alpha, nocc, rhs, x, 1e-26, 1000)
+    assert st == 0
+    w = np.full(cfg.nk, 1.0 / cfg.nk)
+    drho = torch.zeros(cfg.fft, dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    mkpw.pw_drho(sq.ctx, sk.ctx, nocc, w, uk_o, x, drho)
+    torch.cuda.synchronize()
+    # oracle, with the library's eigenvectors
+    dvt = dft.forward(dv)
+    uk_h, uq_h, x_h = uk_o.cpu().numpy(), uq_o.cpu().numpy(), x.cpu().numpy()
+    xs_o, uks_o = [], []
+    worst = 0.0
+    for ik in range(cfg.nk):
+        kk = ham.KPoint(cfg, ik, vt, beta_fn)
+        kq = ham.KPoint(sq.cfg, ik, vt, beta_fn)
+        u1 = _to_oracle(sk, ik, uk_h[ik], kk)
+        u2 = _to_oracle(sq, ik, uq_h[ik], kq).T
+        r = response.dfpt_rhs_q(response.dv_cross_matrix(kq.miller, kk.miller, cfg.fft, dvt) @ u1.T, u2, kq.s)
+        xo = np.array([solvers.dfpt_solve_exact(solvers.dfpt_matrix(kq.h, u2, eps[ik, nu], alpha[ik], kq.s),
+                                                r[:, nu]) for nu in range(nocc)])
+        worst = max(worst, np.max(np.abs(_to_oracle(sq, ik, x_h[ik], kq) - xo)) / np.max(np.abs(xo)))
+        xs_o.append(xo)
+        uks_o.append(u1)
+    ref = response.drho(cfg.fft, w, [kp for kp in (ham.KPoint(cfg, i, vt, beta_fn).miller for i in range(cfg.nk))],
+                        uks_o, [ham.KPoint(sq.cfg, i, vt, beta_fn).miller for i in range(cfg.nk)], xs_o)
+    dr = drho.cpu().numpy()
+    derr = np.max(np.abs(dr - ref)) / np.max(np.abs(ref))
+    print("q end to end: x rel err", worst, "drho rel err", derr, "CG iters", iters.min(), iters.max())
+    assert worst < 1e-9 and derr < 1e-9
