@@ -17,7 +17,8 @@
 //   * drho accumulates, per k, M(G1, G2) = sum_nu conj(u(G1)) du(G2) (register
 //     blocked over 4 x 4 pairs, bands staged in LDS) into bins of the Miller
 //     difference d = m_G2 - m_G1 held in LDS; the per-k bins are summed over k
-//     into the mesh (d mod N) and one inverse transform of the mesh gives
+//     into the mesh (d mod N; 64 chunks of k summed in parallel, then the
+//     chunks in a fixed order) and one inverse transform of the mesh gives
 //     drho(r) = sum_d F(d) exp(2 pi i d.l / N).
 // The transforms of the single mesh (dV(r) -> dV~ with 1/N_r, F -> drho(r))
 // are separable direct sums, one launch per axis.
@@ -146,9 +147,10 @@ __global__ __launch_bounds__(256) void drho_pairs_kernel(int nbnd, const double*
                                                          int nx, cd* __restrict__ part) {
   extern __shared__ char smem[];
   const int nbin = nx * D2 * D3;
+  const int nbin_al = (nbin + 1) & ~1;  // keeps the complex tiles 16-byte aligned
   double* bre = reinterpret_cast<double*>(smem);
-  double* bim = bre + nbin;
-  cd* us = reinterpret_cast<cd*>(bim + nbin);  // [kRB][kRT]
+  double* bim = bre + nbin_al;
+  cd* us = reinterpret_cast<cd*>(bim + nbin_al);  // [kRB][kRT]
   cd* vs = us + kRB * kRT;                     // [kRB][kRT]
   int* ma = reinterpret_cast<int*>(vs + kRB * kRT);  // [3][kRT]
   int* mb = ma + 3 * kRT;                            // [3][kRT]
@@ -229,16 +231,19 @@ __global__ __launch_bounds__(256) void drho_pairs_kernel(int nbnd, const double*
   for (int e = threadIdx.x; e < nbin; e += 256) dst[e] = {bre[e], bim[e]};
 }
 
-// F(l) = sum_k sum of the part[k] bins b with (org_k + b) = l (mod N) on every axis
+// F_c(l) = sum over the k of chunk c (k = c, c + nchunk, ...) of the part[k]
+// bins b with (org_k + b) = l (mod N) on every axis; then F = sum_c F_c in a
+// fixed order (deterministic, no atomics)
 __global__ __launch_bounds__(256) void drho_reduce_kernel(const cd* __restrict__ part, const int* __restrict__ org,
-                                                          int nk, int D1, int D2, int D3, int n1, int n2, int n3,
-                                                          cd* __restrict__ F) {
+                                                          int nk, int nchunk, int D1, int D2, int D3, int n1, int n2,
+                                                          int n3, cd* __restrict__ Fc) {
   const long total = (long)n1 * n2 * n3;
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
+  const int c = blockIdx.y;
   const int l3 = (int)(e % n3), l2 = (int)((e / n3) % n2), l1 = (int)(e / ((long)n2 * n3));
   double sr = 0.0, si = 0.0;
-  for (int k = 0; k < nk; ++k) {
+  for (int k = c; k < nk; k += nchunk) {
     const cd* pk = part + (long)k * D1 * D2 * D3;
     for (int b1 = wrap(l1 - org[3 * k], n1); b1 < D1; b1 += n1)
       for (int b2 = wrap(l2 - org[3 * k + 1], n2); b2 < D2; b2 += n2)
@@ -247,6 +252,18 @@ __global__ __launch_bounds__(256) void drho_reduce_kernel(const cd* __restrict__
           sr += v.x;
           si += v.y;
         }
+  }
+  Fc[(long)c * total + e] = {sr, si};
+}
+
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const cd* __restrict__ Fc, int nchunk, long total,
+                                                         cd* __restrict__ F) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  double sr = 0.0, si = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    sr += Fc[(long)c * total + e].x;
+    si += Fc[(long)c * total + e].y;
   }
   F[e] = {sr, si};
 }
@@ -405,13 +422,15 @@ extern "C" pw_status pw_drho(pw_ctx* ckq, const pw_ctx* ck, int nbnd, const doub
   const size_t tiles = 2 * sizeof(cd) * kRB * kRT + 6 * sizeof(int) * kRT;
   const size_t lds_max = 150 * 1024;
   const size_t per_x = 2 * sizeof(double) * (size_t)D[1] * D[2];
-  if (per_x + tiles > lds_max) return set_err(ckq, PW_EINVAL, "drho: plane-wave spheres too large for the bins");
-  const int nx = (int)std::min<size_t>(D[0], (lds_max - tiles) / per_x);
+  if (per_x + tiles + 2 * sizeof(double) > lds_max) return set_err(ckq, PW_EINVAL, "drho: plane-wave spheres too large for the bins");
+  const int nx = (int)std::min<size_t>(D[0], (lds_max - tiles - 2 * sizeof(double)) / per_x);
   Buf3 b(ckq);
-  cd *part, *F, *tmp;
+  cd *part, *F, *tmp, *Fc;
   int* d_org;
   double* d_w;
+  const int nchunk = std::min(nk, 64);
   RTRY(b.get((size_t)nk * D[0] * D[1] * D[2], &part));
+  RTRY(b.get((size_t)nchunk * nr, &Fc));
   RTRY(b.get((size_t)nr, &F));
   RTRY(b.get((size_t)nr, &tmp));
   RTRY(b.get((size_t)3 * nk, &d_org));
@@ -420,7 +439,7 @@ extern "C" pw_status pw_drho(pw_ctx* ckq, const pw_ctx* ck, int nbnd, const doub
   RHIP(ckq, hipMemcpyAsync(d_w, wk, sizeof(double) * nk, hipMemcpyHostToDevice, st));
   for (int x0 = 0; x0 < D[0]; x0 += nx) {
     const int nxx = std::min(nx, D[0] - x0);
-    const size_t lds = per_x * nxx + tiles;
+    const size_t lds = per_x * nxx + tiles + 2 * sizeof(double);
     RTRY(ensure_lds_limit(ckq, (const void*)drho_pairs_kernel, lds));
     hipLaunchKernelGGL(drho_pairs_kernel, dim3((unsigned)nk), dim3(256), lds, st, nbnd, d_w, ck->d_npw, ck->d_mkey,
                        ck->npwx, (const cd*)psi_k, ckq->d_npw, ckq->d_mkey, ckq->npwx, (const cd*)dpsi_kq, d_org,
@@ -428,7 +447,9 @@ extern "C" pw_status pw_drho(pw_ctx* ckq, const pw_ctx* ck, int nbnd, const doub
     RTRY(check_launch(ckq, "drho_pairs", st));
   }
   const dim3 grid((unsigned)((nr + 255) / 256));
-  hipLaunchKernelGGL(drho_reduce_kernel, grid, dim3(256), 0, st, part, d_org, nk, D[0], D[1], D[2], n1, n2, n3, F);
+  hipLaunchKernelGGL(drho_reduce_kernel, dim3(grid.x, (unsigned)nchunk), dim3(256), 0, st, part, d_org, nk, nchunk,
+                     D[0], D[1], D[2], n1, n2, n3, Fc);
+  hipLaunchKernelGGL(sum_chunks_kernel, grid, dim3(256), 0, st, Fc, nchunk, nr, F);
   // drho(r) = sum_f F(f) exp(+2 pi i f.l / N)
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, F, tmp, n1, n2, n3, 0, 1, 1.0);
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, tmp, F, n1, n2, n3, 1, 1, 1.0);

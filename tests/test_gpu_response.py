@@ -43,7 +43,7 @@ def _to_lib(s, ik, rows, kp):
     return out
 
 
-@pytest.mark.parametrize("cid,step,overlap", [(1, 1, False), (1, 1, True), (3, 256, True)])
+@pytest.mark.parametrize("cid,step,overlap", [(1, 1, False), (1, 1, True), (3, 256, True), (4, 288, False)])
 def test_dfpt_rhs_matches_oracle(cid, step, overlap):
     from paper_2412_01695_amd import mkpw
     cfg0 = synth.make_config(cid)
@@ -77,8 +77,9 @@ def test_dfpt_rhs_matches_oracle(cid, step, overlap):
     assert err <= 1e-12 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("cid,step", [(1, 1), (3, 256)])
+@pytest.mark.parametrize("cid,step", [(1, 1), (3, 256), (4, 288)])
 def test_drho_matches_oracle(cid, step):
+    # the 36^3 case holds more Miller differences than one LDS pass: the bins go in slices
     from paper_2412_01695_amd import mkpw
     cfg0 = synth.make_config(cid)
     cfg = synth.subset(cfg0, np.arange(0, cfg0.nk, step))
