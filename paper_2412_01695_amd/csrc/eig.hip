@@ -39,6 +39,17 @@ constexpr int kEigNev = 32;   // most eigenpairs returned
 
 __device__ __forceinline__ double wave_sum64(double v) { return wave_sum(v); }
 
+// 1/x for the Sturm recurrence and the inverse iteration: the hardware
+// reciprocal estimate refined by two Newton-Raphson steps r <- r + r (1 - x r)
+// (each step squares the relative error), a few dependent operations instead
+// of a full IEEE division
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 // Householder reflector of a column held one component per lane (x on lane
 // l < mm, zero beyond): H = I - g u u^H with H x = beta e_0, beta = -e^{i arg
 // x_0} |x|, u = x - beta e_0; g = 0 (no reflection, beta = x_0) when x has
@@ -237,7 +248,7 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
         for (int i = 1; i < n; ++i) {
-          q = (S.d[i] - x) - S.e[i - 1] * S.e[i - 1] / q;
+          q = (S.d[i] - x) - S.e[i - 1] * S.e[i - 1] * rcp_nr(q);
           if (fabs(q) < pivmin) q = -pivmin;
           cnt += q < 0.0;
         }
@@ -280,7 +291,7 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
         for (int i = 0; i + 1 < n; ++i) {
           const double s = S.e[i], dd = S.d[i + 1] - lm, ee = i + 2 < n ? S.e[i + 1] : 0.0, b1 = y[i + 1];
           if (fabs(c0) >= fabs(s)) {
-            const double l = c0 != 0.0 ? s / c0 : 0.0;
+            const double l = c0 != 0.0 ? s * rcp_nr(c0) : 0.0;
             u0[i] = c0;
             u1[i] = c1;
             u2[i] = 0.0;
@@ -289,7 +300,7 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
             c1 = ee;
             rc = b1 - l * rc;
           } else {
-            const double l = c0 / s;
+            const double l = c0 * rcp_nr(s);
             u0[i] = s;
             u1[i] = dd;
             u2[i] = ee;
@@ -307,7 +318,7 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
         for (int i = n - 1; i >= 0; --i) {
           double piv = u0[i];
           if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
-          const double v = (y[i] - (i + 1 < n ? u1[i] * y1 : 0.0) - (i + 2 < n ? u2[i] * y2 : 0.0)) / piv;
+          const double v = (y[i] - (i + 1 < n ? u1[i] * y1 : 0.0) - (i + 2 < n ? u2[i] * y2 : 0.0)) * rcp_nr(piv);
           y[i] = v;
           y2 = y1;
           y1 = v;
