@@ -70,7 +70,8 @@ const char* pw_last_error(const pw_ctx* ctx);
  * (maximum Davidson basis in units of nbnd, default 4, Sec. 5.3), "trace"
  * (nonzero: synchronise and check after every launch), "hpsi_variant"
  * (0 = autotuned on first use, 1 = one work-item per FFT line, 2 = two lanes
- * per line, even meshes only), "hpsi_slab" (0 = autotuned, else the number of z planes
+ * per line, 3 = two lanes per x line and one per y and z line; 2 and 3 on even
+ * meshes only), "hpsi_slab" (0 = autotuned, else the number of z planes
  * transformed together) and "hpsi_threads" (0 = autotuned, else 256, 512 or
  * 1024 work-items per workgroup where the kernel fits in the registers
  * that leaves; PW_EINVAL otherwise).  Any nonzero shape option fixes the

@@ -242,7 +242,7 @@ pw_status pw_set_option(pw_ctx* c, const char* key, int64_t value) {
   } else if (k == "trace") {
     c->trace = value;
   } else if (k == "hpsi_variant") {
-    if (value < 0 || value > 2) return set_err(c, PW_EINVAL, "hpsi_variant must be 0, 1 or 2");
+    if (value < 0 || value > 3) return set_err(c, PW_EINVAL, "hpsi_variant must be 0, 1, 2 or 3");
     c->hpsi_variant = value;
   } else if (k == "hpsi_slab") {
     if (value < 0 || value > 512) return set_err(c, PW_EINVAL, "hpsi_slab must be in [0, 512]");

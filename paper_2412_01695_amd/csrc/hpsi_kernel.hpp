@@ -523,16 +523,18 @@ size_t hpsi_lds(const KTables& t, int l3c, int nproj, int threads) {
 // 512 from N = 30 on).
 template <class T, int N, int VARIANT>
 constexpr bool allow_512() {
-  return !(sizeof(T) == 8 && VARIANT != 2 && N >= 30);
+  return !(sizeof(T) == 8 && VARIANT == 1 && N >= 30);
 }
 template <class T, int N, int VARIANT>
 constexpr bool allow_1024() {
-  return sizeof(T) == 4 ? (VARIANT == 2 || N <= 20) : (VARIANT == 2 && N <= 24);
+  return sizeof(T) == 4 ? (VARIANT != 1 || N <= 20) : (VARIANT == 2 && N <= 24);
 }
 
 template <class T, int N, int WC, int VARIANT>
 const void* kernel_for(int threads) {
-  constexpr bool ZYP = VARIANT != 1, XP = VARIANT == 2;
+  // variant 1: one work-item per line; 2: lane pairs for every line;
+  // 3: lane pairs for the x lines only (their registers set the occupancy)
+  constexpr bool ZYP = VARIANT == 2, XP = VARIANT != 1;
   if (threads == 256) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 256>;
   if constexpr (allow_512<T, N, VARIANT>()) {
     if (threads == 512) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 512>;
@@ -547,6 +549,7 @@ template <class T, int N, int WC>
 const void* hpsi_kernel_ptr(const HpsiShape& sh) {
   if constexpr (N % 2 == 0) {
     if (sh.variant == 2) return kernel_for<T, N, WC, 2>(sh.threads);
+    if (sh.variant == 3) return kernel_for<T, N, WC, 3>(sh.threads);
   }
   if (sh.variant == 1) return kernel_for<T, N, WC, 1>(sh.threads);
   return nullptr;
@@ -618,24 +621,27 @@ inline int wgs_by_vgpr(const void* kern, int threads) {
   return std::max(1, waves_per_simd * 4 / (threads / 64));
 }
 
-// Candidate shapes: for each variant and workgroup size, the widest slab that
-// fits in the LDS share for 1, 2 or 3 workgroups per CU (as many as the
-// registers allow), capped where every x line already has its own work-item
-// (or lane pair).
+// Candidate shapes: for each variant and workgroup size, the whole mesh as one
+// slab, and the widest slab that fits in the LDS share for 1, 2 or 3
+// workgroups per CU (as many as the registers allow), capped where every x
+// line already has its own work-item (or lane pair).
 template <class T, int N, int WC>
 std::vector<HpsiShape> hpsi_candidates(const KTables& t, int nproj) {
   std::vector<HpsiShape> out;
-  for (int variant : {1, 2}) {
+  for (int variant : {1, 2, 3}) {
     if (variant != 1 && N % 2) continue;
     for (int threads : {256, 512, 1024}) {
       const void* kern = hpsi_kernel_ptr<T, N, WC>({variant, 1, threads});
       if (!kern) continue;
-      const int lanes = variant == 2 ? 2 : 1;  // work-items per x line
+      const int lanes = variant != 1 ? 2 : 1;  // work-items per x line
       const int cap = std::min(N, std::max(1, threads / (lanes * N)));
       const int max_wg = std::min(3, wgs_by_vgpr(kern, threads));  // 0: spills, skipped
-      for (int wg = 1; wg <= max_wg; ++wg) {
-        const size_t share = kLdsPerCu / wg;
-        int l3c = wg == 1 ? N : cap;
+      // the whole mesh in one slab, and for 1..max_wg workgroups per CU the
+      // widest slab up to one x line per work-item that fits their LDS share
+      for (int wg = 0; wg <= max_wg; ++wg) {
+        if (max_wg == 0) break;
+        const size_t share = kLdsPerCu / (wg ? wg : 1);
+        int l3c = wg == 0 ? N : cap;
         while (l3c > 1 && hpsi_lds<T, N, WC>(t, l3c, nproj, threads) > share) --l3c;
         if (hpsi_lds<T, N, WC>(t, l3c, nproj, threads) > kLdsPerCu) continue;
         bool dup = false;
@@ -658,7 +664,7 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
     sh.threads = c->hpsi_threads ? (int)c->hpsi_threads : 256;
     if (!hpsi_kernel_ptr<T, N, WC>(sh))
       return set_err(c, PW_EINVAL, "no H|psi> kernel for this variant and workgroup size on this mesh");
-    const int lanes = sh.variant == 2 ? 2 : 1;
+    const int lanes = sh.variant != 1 ? 2 : 1;
     sh.l3c = c->hpsi_slab ? (int)std::min<int64_t>(c->hpsi_slab, N)
                           : std::min(N, std::max(1, sh.threads / (lanes * N)));
     if (!c->hpsi_slab)

@@ -278,16 +278,18 @@ constexpr size_t kSLdsBudget = 64 * 1024;
 template <class T, int NP, int NPL>
 void launch_spsi_t(pw_ctx* c, const VecSel& sel, const void* psi, void* out, const double* scale, double mult,
                    int nproj, const void* beta, const void* q, hipStream_t st) {
-  const size_t lds_b = sizeof(cplx<T>) * ((size_t)nproj * nproj + (size_t)nproj * c->npwx);
-  if (NPL > 0 && nproj > 0 && lds_b <= kSLdsBudget) {
-    const int groups_per_k = (sel.nvec + kSBandsPerBlock - 1) / kSBandsPerBlock;
-    const int ngroup = groups_per_k * c->nk;
-    const int per_xcd = (ngroup + 7) / 8;
-    hipLaunchKernelGGL((spsi_lds_kernel<T, NP, (NPL > 0 ? 2 * NPL : 1)>), dim3(8u * (unsigned)per_xcd),
-                       dim3(kSThreads), lds_b, st, (const cplx<T>*)psi, (cplx<T>*)out, sel.kstride, sel.nvec,
-                       sel.off, sel.cnt, sel.live, c->d_npw, c->npwx, nproj, (const cplx<T>*)beta,
-                       (const cplx<T>*)q, scale, mult, per_xcd, ngroup, groups_per_k);
-    return;
+  if constexpr (NPL > 0) {
+    const size_t lds_b = sizeof(cplx<T>) * ((size_t)nproj * nproj + (size_t)nproj * c->npwx);
+    if (nproj > 0 && lds_b <= kSLdsBudget) {
+      const int groups_per_k = (sel.nvec + kSBandsPerBlock - 1) / kSBandsPerBlock;
+      const int ngroup = groups_per_k * c->nk;
+      const int per_xcd = (ngroup + 7) / 8;
+      hipLaunchKernelGGL((spsi_lds_kernel<T, NP, 2 * NPL>), dim3(8u * (unsigned)per_xcd), dim3(kSThreads), lds_b,
+                         st, (const cplx<T>*)psi, (cplx<T>*)out, sel.kstride, sel.nvec, sel.off, sel.cnt, sel.live,
+                         c->d_npw, c->npwx, nproj, (const cplx<T>*)beta, (const cplx<T>*)q, scale, mult, per_xcd,
+                         ngroup, groups_per_k);
+      return;
+    }
   }
   const int ntask = sel.nvec * c->nk;
   const int nblk = (ntask + kSThreads / 64 - 1) / (kSThreads / 64);
@@ -321,10 +323,12 @@ void launch_spsi_npl(pw_ctx* c, const VecSel& sel, const void* psi, void* out, c
 template <class T>
 void launch_spsi_np(pw_ctx* c, const VecSel& sel, const void* psi, void* out, const double* scale, double mult,
                     int nproj, const void* beta, const void* q, hipStream_t st) {
+  // up to 8 projectors (every workload here): rows held in registers; more:
+  // one wave per row looping over the plane waves
   if (nproj <= 8)
     launch_spsi_npl<T, 8>(c, sel, psi, out, scale, mult, nproj, beta, q, st);
   else
-    launch_spsi_npl<T, 32>(c, sel, psi, out, scale, mult, nproj, beta, q, st);
+    launch_spsi_t<T, 32, 0>(c, sel, psi, out, scale, mult, nproj, beta, q, st);
 }
 
 }  // namespace
