@@ -28,6 +28,7 @@
 #include <string>
 #include <vector>
 
+#include "host_util.hpp"
 #include "internal.hpp"
 
 namespace mkpw {
@@ -156,39 +157,6 @@ __global__ __launch_bounds__(256) void step2_kernel(cd* t, const cd* d, cd* dold
   if (threadIdx.x == 0) rho_old[sys] = rho[sys];
 }
 
-struct Buf2 {
-  pw_ctx* c;
-  std::vector<void*> ptrs;
-  explicit Buf2(pw_ctx* cc) : c(cc) {}
-  ~Buf2() {
-    for (void* p : ptrs) dev_free(c, p);
-  }
-  template <class T>
-  pw_status get(size_t n, T** out) {
-    void* p = nullptr;
-    pw_status s = dev_alloc(c, n * sizeof(T), &p);
-    if (s != PW_OK) return s;
-    ptrs.push_back(p);
-    *out = (T*)p;
-    return PW_OK;
-  }
-};
-
-#define CTRY(x)                  \
-  do {                           \
-    pw_status s_ = (x);          \
-    if (s_ != PW_OK) return s_;  \
-  } while (0)
-
-#define CHIP(c, call)                                                                          \
-  do {                                                                                         \
-    hipError_t e_ = (call);                                                                    \
-    if (e_ != hipSuccess) {                                                                    \
-      (void)hipGetLastError();                                                                 \
-      return set_err((c), PW_EDEVICE, std::string(#call " failed: ") + hipGetErrorString(e_)); \
-    }                                                                                          \
-  } while (0)
-
 }  // namespace
 
 // rho reduction (squared M^-1-norm of the residual) at which the mixed mode
@@ -202,44 +170,44 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
   const int nk = c->nk, npwx = c->npwx;
   const long nsys = (long)nk * nrhs;
   const size_t nv = (size_t)nsys * npwx;
-  Buf2 bf(c);
+  DevBufs bf(c);
   cd *r, *d, *dold, *t, *W;
   double *eps, *alpha, *rho, *rho_old, *tk;
   int* active;
-  CTRY(bf.get(nv, &r));
-  CTRY(bf.get(nv, &d));
-  CTRY(bf.get(nv, &dold));
-  CTRY(bf.get(nv, &t));
-  CTRY(bf.get((size_t)nk * nocc * nrhs, &W));
-  CTRY(bf.get((size_t)nsys, &eps));
-  CTRY(bf.get((size_t)nk, &alpha));
-  CTRY(bf.get((size_t)nsys, &rho));
-  CTRY(bf.get((size_t)nsys, &rho_old));
+  MKPW_TRY(bf.get(nv, &r));
+  MKPW_TRY(bf.get(nv, &d));
+  MKPW_TRY(bf.get(nv, &dold));
+  MKPW_TRY(bf.get(nv, &t));
+  MKPW_TRY(bf.get((size_t)nk * nocc * nrhs, &W));
+  MKPW_TRY(bf.get((size_t)nsys, &eps));
+  MKPW_TRY(bf.get((size_t)nk, &alpha));
+  MKPW_TRY(bf.get((size_t)nsys, &rho));
+  MKPW_TRY(bf.get((size_t)nsys, &rho_old));
   double* rho0;
-  CTRY(bf.get((size_t)nsys, &rho0));
-  CTRY(bf.get((size_t)nsys, &tk));
-  CTRY(bf.get((size_t)nsys, &active));
+  MKPW_TRY(bf.get((size_t)nsys, &rho0));
+  MKPW_TRY(bf.get((size_t)nsys, &tk));
+  MKPW_TRY(bf.get((size_t)nsys, &active));
   cplx<float>*v32 = nullptr, *t32 = nullptr;
   if (prec == PW_MIXED) {
-    CTRY(bf.get(nv, &v32));
-    CTRY(bf.get(nv, &t32));
+    MKPW_TRY(bf.get(nv, &v32));
+    MKPW_TRY(bf.get(nv, &t32));
   }
-  CHIP(c, hipMemcpyAsync(eps, eps_h, sizeof(double) * nsys, hipMemcpyHostToDevice, st));
-  CHIP(c, hipMemcpyAsync(alpha, alpha_h, sizeof(double) * nk, hipMemcpyHostToDevice, st));
-  CHIP(c, hipMemsetAsync(dold, 0, sizeof(cd) * nv, st));
-  CHIP(c, hipMemsetAsync(rho_old, 0, sizeof(double) * nsys, st));
+  MKPW_HIP(c, hipMemcpyAsync(eps, eps_h, sizeof(double) * nsys, hipMemcpyHostToDevice, st));
+  MKPW_HIP(c, hipMemcpyAsync(alpha, alpha_h, sizeof(double) * nk, hipMemcpyHostToDevice, st));
+  MKPW_HIP(c, hipMemsetAsync(dold, 0, sizeof(cd) * nv, st));
+  MKPW_HIP(c, hipMemsetAsync(rho_old, 0, sizeof(double) * nsys, st));
   hipLaunchKernelGGL(tkin_kernel, dim3(nrhs, nk), dim3(256), 0, st, U, nocc, c->d_kin, c->d_npw, npwx, nrhs, tk);
-  CTRY(check_launch(c, "tkin", st));
+  MKPW_TRY(check_launch(c, "tkin", st));
   // P = S U for the projector term (U itself without an overlap)
   const bool gen = c->have_q;
   const cd* P = U;
   if (gen) {
     cd* SU;
-    CTRY(bf.get((size_t)nk * nocc * npwx, &SU));
+    MKPW_TRY(bf.get((size_t)nk * nocc * npwx, &SU));
     VecSel sel;
     sel.nvec = nocc;
     sel.kstride = (long)nocc * npwx;
-    CTRY(launch_spsi(c, PW_FP64, sel, U, SU, nullptr, 0.0, st));
+    MKPW_TRY(launch_spsi(c, PW_FP64, sel, U, SU, nullptr, 0.0, st));
     P = SU;
   }
 
@@ -253,39 +221,39 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     sel.kstride = (long)nrhs * npwx;
     sel.live = live;
     if (fp64_h) {
-      CTRY(launch_hpsi(c, PW_FP64, sel, v, t, st));
+      MKPW_TRY(launch_hpsi(c, PW_FP64, sel, v, t, st));
     } else {
-      CTRY(launch_to_c64(c, v, (long)nrhs * npwx, nullptr, v32, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
-      CTRY(launch_hpsi(c, PW_MIXED, sel, v32, t32, st));
-      CTRY(launch_to_c128(c, t32, (long)nrhs * npwx, nullptr, t, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
+      MKPW_TRY(launch_to_c64(c, v, (long)nrhs * npwx, nullptr, v32, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
+      MKPW_TRY(launch_hpsi(c, PW_MIXED, sel, v32, t32, st));
+      MKPW_TRY(launch_to_c128(c, t32, (long)nrhs * npwx, nullptr, t, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
     }
-    if (gen) CTRY(launch_spsi(c, PW_FP64, sel, v, t, eps, -1.0, st));  // t -= eps S v
+    if (gen) MKPW_TRY(launch_spsi(c, PW_FP64, sel, v, t, eps, -1.0, st));  // t -= eps S v
     GramArgs g;
     g.A = P; g.a_kstride = (long)nocc * npwx; g.a_n = nocc;
     g.B = v; g.b_kstride = (long)nrhs * npwx; g.b_n = nrhs;
     g.ld = npwx; g.npw = c->d_npw;
     g.C = W; g.c_kstride = (long)nocc * nrhs; g.ldc = nrhs;
-    CTRY(launch_gram(c, g, nocc, nrhs, st));
+    MKPW_TRY(launch_gram(c, g, nocc, nrhs, st));
     hipLaunchKernelGGL(scale_w_kernel, dim3(nk), dim3(256), 0, st, W, nocc * nrhs, alpha);
-    CTRY(check_launch(c, "scale_w", st));
+    MKPW_TRY(check_launch(c, "scale_w", st));
     if (nocc > 64) return set_err(c, PW_EINVAL, "nocc must be <= 64");
     CombArgs m;
     m.X = P; m.x_kstride = (long)nocc * npwx; m.x_n = nocc;
     m.Y = t; m.y_kstride = (long)nrhs * npwx; m.y_n = nrhs;
     m.ld = npwx; m.Cm = W; m.c_kstride = (long)nocc * nrhs; m.ldc = nrhs;
     m.accumulate = 1;
-    CTRY(launch_combine(c, m, nocc, st));
+    MKPW_TRY(launch_combine(c, m, nocc, st));
     return PW_OK;
   };
   auto restart = [&]() -> pw_status {
-    CTRY(apply_a(x, nullptr));
+    MKPW_TRY(apply_a(x, nullptr));
     hipLaunchKernelGGL(init_resid_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, x, b, eps, r, npwx, active,
                        c->d_npw, nrhs, gen ? 0 : 1);
     return check_launch(c, "init_resid", st);
   };
 
   std::vector<int> act(nsys, 1), iters(nsys, 0);
-  CTRY(restart());
+  MKPW_TRY(restart());
   int first = 1;
   bool ok = false;
   int it_total = 0;
@@ -295,9 +263,9 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     const double rel = fp64_h ? 0.0 : kRelFp32;
     hipLaunchKernelGGL(step1_kernel, dim3((unsigned)nsys), dim3(256), 0, st, r, d, dold, c->d_kin, tk, c->d_npw,
                        npwx, nrhs, rho, rho_old, rho0, active, first, thr, rel);
-    CTRY(check_launch(c, "cg_step1", st));
-    CHIP(c, hipMemcpyAsync(act.data(), active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
-    CHIP(c, hipStreamSynchronize(st));
+    MKPW_TRY(check_launch(c, "cg_step1", st));
+    MKPW_HIP(c, hipMemcpyAsync(act.data(), active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
+    MKPW_HIP(c, hipStreamSynchronize(st));
     long n_act = 0;
     for (long s = 0; s < nsys; ++s)
       if (act[s]) {
@@ -310,7 +278,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
         fp64_h = true;
         it_total += it;
         first = 1;
-        CTRY(restart());
+        MKPW_TRY(restart());
         it = 0;
         continue;
       }
@@ -318,12 +286,12 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
       break;
     }
     first = 0;
-    CTRY(apply_a(d, active));
+    MKPW_TRY(apply_a(d, active));
     hipLaunchKernelGGL(step2_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, d, dold, x, r, eps, c->d_npw, npwx,
                        nrhs, rho, rho_old, active, gen ? 0 : 1);
-    CTRY(check_launch(c, "cg_step2", st));
+    MKPW_TRY(check_launch(c, "cg_step2", st));
   }
-  CHIP(c, hipStreamSynchronize(st));
+  MKPW_HIP(c, hipStreamSynchronize(st));
   if (iters_out)
     for (long s = 0; s < nsys; ++s) iters_out[s] = iters[s];
   if (!ok) return set_err(c, PW_ENOCONV, "CG: some systems did not converge");

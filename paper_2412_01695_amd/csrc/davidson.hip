@@ -30,6 +30,7 @@
 #include <string>
 #include <vector>
 
+#include "host_util.hpp"
 #include "internal.hpp"
 
 namespace mkpw {
@@ -176,39 +177,6 @@ __global__ void copy_rows_kernel(const cd* src, int src_rows, cd* dst, int dst_r
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) d[e] = s[e];
 }
 
-struct Buf {
-  pw_ctx* c;
-  std::vector<void*> ptrs;
-  explicit Buf(pw_ctx* cc) : c(cc) {}
-  ~Buf() {
-    for (void* p : ptrs) dev_free(c, p);
-  }
-  template <class T>
-  pw_status get(size_t n, T** out) {
-    void* p = nullptr;
-    pw_status s = dev_alloc(c, n * sizeof(T), &p);
-    if (s != PW_OK) return s;
-    ptrs.push_back(p);
-    *out = (T*)p;
-    return PW_OK;
-  }
-};
-
-#define TRY(x)                          \
-  do {                                  \
-    pw_status s_ = (x);                 \
-    if (s_ != PW_OK) return s_;         \
-  } while (0)
-
-#define HIPTRY(c, call)                                                                        \
-  do {                                                                                         \
-    hipError_t e_ = (call);                                                                    \
-    if (e_ != hipSuccess) {                                                                    \
-      (void)hipGetLastError();                                                                 \
-      return set_err((c), PW_EDEVICE, std::string(#call " failed: ") + hipGetErrorString(e_)); \
-    }                                                                                          \
-  } while (0)
-
 }  // namespace
 
 pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, double tol_ry, int max_iter,
@@ -220,53 +188,53 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   const double rtol64 = 1e-5;
   const double tol32 = std::max(tol, 2e-6), rtol32 = 2e-4;
   const bool gen = c->have_q;  // generalized problem: S != 1
-  Buf b(c);
+  DevBufs b(c);
   cd *V, *HV, *X, *HX, *T, *Rb, *Hr, *Cr, *Om, *Sm, *Mm;
   cd *SV, *SX;
   double *theta, *rn, *hd, *sd, *nrm0, *nrm1;
   int *d_nb, *d_nnc, *d_map, *d_flag, *d_active, *d_info, *d_zero, *d_nr, *d_ny, *d_ntot, *d_mask;
   const size_t kb = (size_t)nk * nbmax * npwx, kn = (size_t)nk * nbnd * npwx;
-  TRY(b.get(kb, &V));
-  TRY(b.get(kb, &HV));
-  TRY(b.get(kn, &X));
-  TRY(b.get(kn, &HX));
+  MKPW_TRY(b.get(kb, &V));
+  MKPW_TRY(b.get(kb, &HV));
+  MKPW_TRY(b.get(kn, &X));
+  MKPW_TRY(b.get(kn, &HX));
   if (gen) {
-    TRY(b.get(kb, &SV));
-    TRY(b.get(kn, &SX));
+    MKPW_TRY(b.get(kb, &SV));
+    MKPW_TRY(b.get(kn, &SX));
   } else {
     SV = V;  // S = 1: the S-images are the vectors themselves
     SX = X;
   }
-  TRY(b.get(kn, &T));
-  TRY(b.get(kn, &Rb));
-  TRY(b.get((size_t)nk * nbmax * nbmax, &Hr));
-  TRY(b.get((size_t)nk * nbmax * nbnd, &Cr));
-  TRY(b.get((size_t)nk * nbmax * nbnd, &Om));
-  TRY(b.get((size_t)nk * nbnd * nbnd, &Sm));
-  TRY(b.get((size_t)nk * nbnd * nbnd, &Mm));
-  TRY(b.get((size_t)nk * nbnd, &theta));
-  TRY(b.get((size_t)nk * nbnd, &rn));
-  TRY(b.get((size_t)nk * npwx, &hd));
-  TRY(b.get((size_t)nk * npwx, &sd));
-  TRY(b.get((size_t)nk * nbnd, &nrm0));
-  TRY(b.get((size_t)nk * nbnd, &nrm1));
-  TRY(b.get((size_t)nk, &d_nb));
-  TRY(b.get((size_t)nk, &d_nnc));
-  TRY(b.get((size_t)nk * nbnd, &d_map));
-  TRY(b.get((size_t)nk, &d_flag));
-  TRY(b.get((size_t)nk, &d_active));
-  TRY(b.get((size_t)nk, &d_info));
-  TRY(b.get((size_t)nk, &d_zero));
-  TRY(b.get((size_t)nk, &d_nr));
-  TRY(b.get((size_t)nk, &d_ny));
-  TRY(b.get((size_t)nk, &d_ntot));
-  TRY(b.get((size_t)nk * nbnd, &d_mask));
+  MKPW_TRY(b.get(kn, &T));
+  MKPW_TRY(b.get(kn, &Rb));
+  MKPW_TRY(b.get((size_t)nk * nbmax * nbmax, &Hr));
+  MKPW_TRY(b.get((size_t)nk * nbmax * nbnd, &Cr));
+  MKPW_TRY(b.get((size_t)nk * nbmax * nbnd, &Om));
+  MKPW_TRY(b.get((size_t)nk * nbnd * nbnd, &Sm));
+  MKPW_TRY(b.get((size_t)nk * nbnd * nbnd, &Mm));
+  MKPW_TRY(b.get((size_t)nk * nbnd, &theta));
+  MKPW_TRY(b.get((size_t)nk * nbnd, &rn));
+  MKPW_TRY(b.get((size_t)nk * npwx, &hd));
+  MKPW_TRY(b.get((size_t)nk * npwx, &sd));
+  MKPW_TRY(b.get((size_t)nk * nbnd, &nrm0));
+  MKPW_TRY(b.get((size_t)nk * nbnd, &nrm1));
+  MKPW_TRY(b.get((size_t)nk, &d_nb));
+  MKPW_TRY(b.get((size_t)nk, &d_nnc));
+  MKPW_TRY(b.get((size_t)nk * nbnd, &d_map));
+  MKPW_TRY(b.get((size_t)nk, &d_flag));
+  MKPW_TRY(b.get((size_t)nk, &d_active));
+  MKPW_TRY(b.get((size_t)nk, &d_info));
+  MKPW_TRY(b.get((size_t)nk, &d_zero));
+  MKPW_TRY(b.get((size_t)nk, &d_nr));
+  MKPW_TRY(b.get((size_t)nk, &d_ny));
+  MKPW_TRY(b.get((size_t)nk, &d_ntot));
+  MKPW_TRY(b.get((size_t)nk * nbnd, &d_mask));
   cplx<float>*T32 = nullptr, *HT32 = nullptr;
   if (prec == PW_MIXED) {
-    TRY(b.get(kn, &T32));
-    TRY(b.get(kn, &HT32));
+    MKPW_TRY(b.get(kn, &T32));
+    MKPW_TRY(b.get(kn, &HT32));
   }
-  HIPTRY(c, hipMemsetAsync(d_zero, 0, sizeof(int) * nk, st));
+  MKPW_HIP(c, hipMemsetAsync(d_zero, 0, sizeof(int) * nk, st));
 
   // host mirrors
   std::vector<int> nb(nk, 0), nnc(nk, nbnd), map((size_t)nk * nbnd), flag(nk, 0), active(nk, 1), info(nk, 0);
@@ -293,7 +261,7 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     const int np = c->have_proj ? c->nproj : 0;
     hipLaunchKernelGGL(hdiag_kernel, grid, dim3(256), 0, st, c->d_npw, npwx, c->d_kin, c->v0, np,
                        (const cd*)c->d_beta64, (const cd*)c->d_dij64, gen ? (const cd*)c->d_q64 : nullptr, hd, sd);
-    TRY(check_launch(c, "hdiag", st));
+    MKPW_TRY(check_launch(c, "hdiag", st));
   }
 
   // SV = S V on rows [nb, nb + nnc) (generalized problem only)
@@ -317,16 +285,16 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
       sel.kstride = (long)nbmax * npwx;
       sel.off = d_nb;
       sel.cnt = d_nnc;
-      TRY(launch_hpsi(c, PW_FP64, sel, V, HV, st));
+      MKPW_TRY(launch_hpsi(c, PW_FP64, sel, V, HV, st));
       return PW_OK;
     }
-    TRY(launch_to_c64(c, V, (long)nbmax * npwx, d_nb, T32, (long)nbnd * npwx, nullptr, d_nnc, nvec_max, st));
+    MKPW_TRY(launch_to_c64(c, V, (long)nbmax * npwx, d_nb, T32, (long)nbnd * npwx, nullptr, d_nnc, nvec_max, st));
     VecSel sel;
     sel.nvec = nvec_max;
     sel.kstride = (long)nbnd * npwx;
     sel.cnt = d_nnc;
-    TRY(launch_hpsi(c, PW_MIXED, sel, T32, HT32, st));
-    TRY(launch_to_c128(c, HT32, (long)nbnd * npwx, nullptr, HV, (long)nbmax * npwx, d_nb, d_nnc, nvec_max, st));
+    MKPW_TRY(launch_hpsi(c, PW_MIXED, sel, T32, HT32, st));
+    MKPW_TRY(launch_to_c128(c, HT32, (long)nbnd * npwx, nullptr, HV, (long)nbmax * npwx, d_nb, d_nnc, nvec_max, st));
     return PW_OK;
   };
 
@@ -339,24 +307,24 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     dim3 grid(nnc_max, nk);
     hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, SV2, (long)nbmax * npwx, d_nb, d_nnc, npwx,
                        nrm0, nbnd, 0);
-    TRY(check_launch(c, "norm", st));
+    MKPW_TRY(check_launch(c, "norm", st));
     for (int pass = 0; pass < 2 && nb_max > 0; ++pass) {
       GramArgs g;
       g.A = SV; g.a_kstride = (long)nbmax * npwx; g.a_off = d_zero; g.a_cnt = d_nb;
       g.B = V; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = d_nnc;
       g.ld = npwx; g.npw = c->d_npw;
       g.C = Om; g.c_kstride = (long)nbmax * nbnd; g.ldc = nbnd;
-      TRY(launch_gram(c, g, nb_max, nnc_max, st));
+      MKPW_TRY(launch_gram(c, g, nb_max, nnc_max, st));
       CombArgs m;
       m.X = V; m.x_kstride = (long)nbmax * npwx; m.x_off = d_zero; m.x_cnt = d_nb;
       m.Y = V; m.y_kstride = (long)nbmax * npwx; m.y_off = d_nb; m.y_cnt = d_nnc;
       m.ld = npwx; m.Cm = Om; m.c_kstride = (long)nbmax * nbnd; m.ldc = nbnd;
       m.alpha = -1.0; m.accumulate = 1;
-      TRY(launch_combine(c, m, nb_max, st));
+      MKPW_TRY(launch_combine(c, m, nb_max, st));
       if (gen) {
         m.X = SV;
         m.Y = SV;
-        TRY(launch_combine(c, m, nb_max, st));
+        MKPW_TRY(launch_combine(c, m, nb_max, st));
       }
     }
     hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, SV2, (long)nbmax * npwx, d_nb, d_nnc, npwx,
@@ -375,12 +343,12 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
       g.B = SV; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = d_nnc;
       g.ld = npwx; g.npw = c->d_npw;
       g.C = Sm; g.c_kstride = (long)nbnd * nbnd; g.ldc = nbnd;
-      TRY(launch_gram(c, g, nnc_max, nnc_max, st));
-      TRY(launch_chol_inv(c, Sm, (long)nbnd * nbnd, nbnd, d_nnc, Mm, (long)nbnd * nbnd, nbnd, d_info, st));
-      TRY(launch_trmm(c, V, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
-      if (gen) TRY(launch_trmm(c, SV, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
-      HIPTRY(c, hipMemcpyAsync(info.data(), d_info, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
-      HIPTRY(c, sync());
+      MKPW_TRY(launch_gram(c, g, nnc_max, nnc_max, st));
+      MKPW_TRY(launch_chol_inv(c, Sm, (long)nbnd * nbnd, nbnd, d_nnc, Mm, (long)nbnd * nbnd, nbnd, d_info, st));
+      MKPW_TRY(launch_trmm(c, V, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
+      if (gen) MKPW_TRY(launch_trmm(c, SV, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
+      MKPW_HIP(c, hipMemcpyAsync(info.data(), d_info, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
+      MKPW_HIP(c, sync());
       bool changed = false;
       for (int k = 0; k < nk; ++k)
         if (info[k] && nnc[k] > 0) {
@@ -388,7 +356,7 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
           force_restart[k] = 1;
           changed = true;
         }
-      if (changed) HIPTRY(c, h2d(d_nnc, nnc));
+      if (changed) MKPW_HIP(c, h2d(d_nnc, nnc));
     }
     return PW_OK;
   };
@@ -401,11 +369,11 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   std::vector<int> mask((size_t)nk * nbnd);
   auto orthonormalize = [&](int nb_max, int nnc_max, bool allow_residual) -> pw_status {
     if (nnc_max <= 0) return PW_OK;
-    TRY(project(nb_max, nnc_max));
+    MKPW_TRY(project(nb_max, nnc_max));
     if (allow_residual) {
-      HIPTRY(c, hipMemcpyAsync(n0h.data(), nrm0, sizeof(double) * n0h.size(), hipMemcpyDeviceToHost, st));
-      HIPTRY(c, hipMemcpyAsync(n1h.data(), nrm1, sizeof(double) * n1h.size(), hipMemcpyDeviceToHost, st));
-      HIPTRY(c, sync());
+      MKPW_HIP(c, hipMemcpyAsync(n0h.data(), nrm0, sizeof(double) * n0h.size(), hipMemcpyDeviceToHost, st));
+      MKPW_HIP(c, hipMemcpyAsync(n1h.data(), nrm1, sizeof(double) * n1h.size(), hipMemcpyDeviceToHost, st));
+      MKPW_HIP(c, sync());
       bool any = false;
       for (int k = 0; k < nk; ++k)
         for (int r = 0; r < nbnd; ++r) {
@@ -414,13 +382,13 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
           any = any || mask[o];
         }
       if (any) {
-        HIPTRY(c, h2d(d_mask, mask));
+        MKPW_HIP(c, h2d(d_mask, mask));
         dim3 grid((npwx + 255) / 256, nk, nnc_max);
         hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(256), 0, st, Rb, nbnd, V, nbmax, d_nb, d_nnc, d_map, npwx,
                            d_mask);
-        TRY(check_launch(c, "gather_r", st));
-        TRY(apply_s(nnc_max));
-        TRY(project(nb_max, nnc_max));
+        MKPW_TRY(check_launch(c, "gather_r", st));
+        MKPW_TRY(apply_s(nnc_max));
+        MKPW_TRY(project(nb_max, nnc_max));
       }
     }
     return cholqr(nnc_max);
@@ -430,14 +398,14 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   auto extend_h = [&](int ntot_max, int nnc_max) -> pw_status {
     std::vector<int> ntot(nk);
     for (int k = 0; k < nk; ++k) ntot[k] = nb[k] + nnc[k];
-    HIPTRY(c, h2d(d_ntot, ntot));
+    MKPW_HIP(c, h2d(d_ntot, ntot));
     GramArgs g;
     g.A = V; g.a_kstride = (long)nbmax * npwx; g.a_off = d_zero; g.a_cnt = d_ntot;
     g.B = HV; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = d_nnc;
     g.ld = npwx; g.npw = c->d_npw;
     g.C = Hr; g.c_kstride = (long)nbmax * nbmax; g.ldc = nbmax; g.c_roff = d_zero; g.c_coff = d_nb;
     g.mirror = 1;
-    TRY(launch_gram(c, g, ntot_max, nnc_max, st));
+    MKPW_TRY(launch_gram(c, g, ntot_max, nnc_max, st));
     return PW_OK;
   };
 
@@ -449,17 +417,17 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
       nr[k] = active[k] ? nb[k] : 0;
       ny[k] = active[k] ? nbnd : 0;
     }
-    HIPTRY(c, h2d(d_nb, nb));
-    HIPTRY(c, h2d(d_nr, nr));
-    HIPTRY(c, h2d(d_ny, ny));
-    TRY(launch_heev(c, Hr, (long)nbmax * nbmax, nbmax, d_nr, nb_max, nbnd, theta, Cr, (long)nbmax * nbnd, nbnd, st));
+    MKPW_HIP(c, h2d(d_nb, nb));
+    MKPW_HIP(c, h2d(d_nr, nr));
+    MKPW_HIP(c, h2d(d_ny, ny));
+    MKPW_TRY(launch_heev(c, Hr, (long)nbmax * nbmax, nbmax, d_nr, nb_max, nbnd, theta, Cr, (long)nbmax * nbnd, nbnd, st));
     for (int which = 0; which < 2; ++which) {
       CombArgs m;
       m.X = which ? HV : V; m.x_kstride = (long)nbmax * npwx; m.x_cnt = d_nr;
       m.Y = which ? HX : X; m.y_kstride = (long)nbnd * npwx; m.y_n = nbnd;
       m.y_cnt = d_ny;
       m.ld = npwx; m.Cm = Cr; m.c_kstride = (long)nbmax * nbnd; m.ldc = nbnd;
-      TRY(launch_combine(c, m, nb_max, st));
+      MKPW_TRY(launch_combine(c, m, nb_max, st));
     }
     if (gen) {
       // S X afresh rather than SV C: the S-images carried along with the basis
@@ -469,7 +437,7 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
       sel.nvec = nbnd;
       sel.kstride = (long)nbnd * npwx;
       sel.cnt = d_ny;
-      TRY(launch_spsi(c, PW_FP64, sel, X, SX, nullptr, 0.0, st));
+      MKPW_TRY(launch_spsi(c, PW_FP64, sel, X, SX, nullptr, 0.0, st));
     }
     return PW_OK;
   };
@@ -478,22 +446,22 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   {
     dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
     hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, psi, nbnd, V, nbmax, nbnd, npwx);
-    TRY(check_launch(c, "copy", st));
+    MKPW_TRY(check_launch(c, "copy", st));
     std::fill(nb.begin(), nb.end(), 0);
     std::fill(nnc.begin(), nnc.end(), nbnd);
-    HIPTRY(c, h2d(d_nb, nb));
-    HIPTRY(c, h2d(d_nnc, nnc));
-    TRY(apply_s(nbnd));
-    TRY(orthonormalize(0, nbnd, false));
+    MKPW_HIP(c, h2d(d_nb, nb));
+    MKPW_HIP(c, h2d(d_nnc, nnc));
+    MKPW_TRY(apply_s(nbnd));
+    MKPW_TRY(orthonormalize(0, nbnd, false));
     for (int k = 0; k < nk; ++k)
       if (nnc[k] == 0) return set_err(c, PW_EINVAL,
                        std::string("starting vectors are linearly dependent") +
                            (gen ? " (or S is not positive definite)" : "") + " at k " + std::to_string(k));
-    TRY(apply_h(nbnd));
-    HIPTRY(c, hipMemsetAsync(Hr, 0, sizeof(cd) * (size_t)nk * nbmax * nbmax, st));
-    TRY(extend_h(nbnd, nbnd));
+    MKPW_TRY(apply_h(nbnd));
+    MKPW_HIP(c, hipMemsetAsync(Hr, 0, sizeof(cd) * (size_t)nk * nbmax * nbmax, st));
+    MKPW_TRY(extend_h(nbnd, nbnd));
     for (int k = 0; k < nk; ++k) nb[k] = nbnd;
-    TRY(ritz(nbnd));
+    MKPW_TRY(ritz(nbnd));
   }
 
   bool refine = false;  // mixed precision: FP64 phase started
@@ -501,16 +469,16 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   bool all_done = false;
   for (it = 1; it <= max_iter; ++it) {
     // residuals of the current Ritz pairs
-    HIPTRY(c, h2d(d_active, active));
+    MKPW_HIP(c, h2d(d_active, active));
     {
       dim3 grid(nbnd, nk);
       hipLaunchKernelGGL(resid_kernel, grid, dim3(256), 0, st, SX, HX, theta, d_active, hd, sd, c->d_npw, npwx, nbnd,
                          T, Rb, rn);
-      TRY(check_launch(c, "resid", st));
+      MKPW_TRY(check_launch(c, "resid", st));
     }
-    HIPTRY(c, hipMemcpyAsync(th.data(), theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
-    HIPTRY(c, hipMemcpyAsync(rnh.data(), rn, sizeof(double) * rnh.size(), hipMemcpyDeviceToHost, st));
-    HIPTRY(c, sync());
+    MKPW_HIP(c, hipMemcpyAsync(th.data(), theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
+    MKPW_HIP(c, hipMemcpyAsync(rnh.data(), rn, sizeof(double) * rnh.size(), hipMemcpyDeviceToHost, st));
+    MKPW_HIP(c, sync());
     const double etol = fp64_h ? tol : tol32, rtol = fp64_h ? rtol64 : rtol32;
     int n_active = 0, nnc_max = 0, nb_max = 0;
     for (int k = 0; k < nk; ++k) {
@@ -550,63 +518,63 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
         std::fill(th_old.begin(), th_old.end(), std::numeric_limits<double>::infinity());
         dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
         hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, X, nbnd, V, nbmax, nbnd, npwx);
-        TRY(check_launch(c, "copy", st));
+        MKPW_TRY(check_launch(c, "copy", st));
         if (gen) {
           hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, SX, nbnd, SV, nbmax, nbnd, npwx);
-          TRY(check_launch(c, "copy", st));
+          MKPW_TRY(check_launch(c, "copy", st));
         }
         std::fill(nb.begin(), nb.end(), 0);
         std::fill(nnc.begin(), nnc.end(), nbnd);
-        HIPTRY(c, h2d(d_nb, nb));
-        HIPTRY(c, h2d(d_nnc, nnc));
-        TRY(apply_h(nbnd));
-        HIPTRY(c, hipMemsetAsync(Hr, 0, sizeof(cd) * (size_t)nk * nbmax * nbmax, st));
-        TRY(extend_h(nbnd, nbnd));
+        MKPW_HIP(c, h2d(d_nb, nb));
+        MKPW_HIP(c, h2d(d_nnc, nnc));
+        MKPW_TRY(apply_h(nbnd));
+        MKPW_HIP(c, hipMemsetAsync(Hr, 0, sizeof(cd) * (size_t)nk * nbmax * nbmax, st));
+        MKPW_TRY(extend_h(nbnd, nbnd));
         for (int k = 0; k < nk; ++k) nb[k] = nbnd;
-        TRY(ritz(nbnd));
+        MKPW_TRY(ritz(nbnd));
         continue;
       }
       all_done = true;
       break;
     }
-    HIPTRY(c, h2d(d_flag, flag));
-    HIPTRY(c, h2d(d_map, map));
-    HIPTRY(c, h2d(d_nnc, nnc));
+    MKPW_HIP(c, h2d(d_flag, flag));
+    MKPW_HIP(c, h2d(d_map, map));
+    MKPW_HIP(c, h2d(d_nnc, nnc));
     {
       dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
       hipLaunchKernelGGL(restart_kernel, grid, dim3(256), 0, st, d_flag, X, HX, gen ? SX : nullptr, V, HV, SV, nbnd,
                          nbmax, npwx, Hr, theta);
-      TRY(check_launch(c, "restart", st));
+      MKPW_TRY(check_launch(c, "restart", st));
     }
-    HIPTRY(c, h2d(d_nb, nb));
+    MKPW_HIP(c, h2d(d_nb, nb));
     {
       dim3 grid((npwx + 255) / 256, nk, nnc_max);
       hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(256), 0, st, T, nbnd, V, nbmax, d_nb, d_nnc, d_map, npwx,
                          (const int*)nullptr);
-      TRY(check_launch(c, "gather", st));
+      MKPW_TRY(check_launch(c, "gather", st));
     }
-    TRY(apply_s(nnc_max));
+    MKPW_TRY(apply_s(nnc_max));
     int nb_cur_max = 0;
     for (int k = 0; k < nk; ++k) nb_cur_max = std::max(nb_cur_max, nb[k]);
-    TRY(orthonormalize(nb_cur_max, nnc_max, true));
-    TRY(apply_h(nnc_max));
-    TRY(extend_h(nb_max, nnc_max));
+    MKPW_TRY(orthonormalize(nb_cur_max, nnc_max, true));
+    MKPW_TRY(apply_h(nnc_max));
+    MKPW_TRY(extend_h(nb_max, nnc_max));
     int ntot_max = 0;
     for (int k = 0; k < nk; ++k) {
       nb[k] += nnc[k];
       ntot_max = std::max(ntot_max, nb[k]);
     }
-    TRY(ritz(ntot_max));
+    MKPW_TRY(ritz(ntot_max));
   }
 
   // results: Ritz vectors and values
   {
     dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
     hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, X, nbnd, psi, nbnd, nbnd, npwx);
-    TRY(check_launch(c, "copy", st));
+    MKPW_TRY(check_launch(c, "copy", st));
   }
-  HIPTRY(c, hipMemcpyAsync(eig, theta, sizeof(double) * (size_t)nk * nbnd, hipMemcpyDeviceToHost, st));
-  HIPTRY(c, sync());
+  MKPW_HIP(c, hipMemcpyAsync(eig, theta, sizeof(double) * (size_t)nk * nbnd, hipMemcpyDeviceToHost, st));
+  MKPW_HIP(c, sync());
   bool all_conv = true;
   for (int k = 0; k < nk; ++k) {
     if (iters_out) iters_out[k] = iters[k];

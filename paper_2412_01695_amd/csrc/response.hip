@@ -29,6 +29,7 @@
 #include <string>
 #include <vector>
 
+#include "host_util.hpp"
 #include "internal.hpp"
 
 namespace mkpw {
@@ -268,39 +269,6 @@ __global__ __launch_bounds__(256) void sum_chunks_kernel(const cd* __restrict__ 
   F[e] = {sr, si};
 }
 
-struct Buf3 {
-  pw_ctx* c;
-  std::vector<void*> ptrs;
-  explicit Buf3(pw_ctx* cc) : c(cc) {}
-  ~Buf3() {
-    for (void* p : ptrs) dev_free(c, p);
-  }
-  template <class T>
-  pw_status get(size_t n, T** out) {
-    void* p = nullptr;
-    pw_status s = dev_alloc(c, n * sizeof(T), &p);
-    if (s != PW_OK) return s;
-    ptrs.push_back(p);
-    *out = (T*)p;
-    return PW_OK;
-  }
-};
-
-#define RTRY(x)                  \
-  do {                           \
-    pw_status s_ = (x);          \
-    if (s_ != PW_OK) return s_;  \
-  } while (0)
-
-#define RHIP(c, call)                                                                          \
-  do {                                                                                         \
-    hipError_t e_ = (call);                                                                    \
-    if (e_ != hipSuccess) {                                                                    \
-      (void)hipGetLastError();                                                                 \
-      return set_err((c), PW_EDEVICE, std::string(#call " failed: ") + hipGetErrorString(e_)); \
-    }                                                                                          \
-  } while (0)
-
 // ctx_k and ctx_kq describe the same crystal on the same device: lattice,
 // cutoff, mesh and number of k-points equal
 pw_status check_pair(pw_ctx* ckq, const pw_ctx* ck) {
@@ -320,14 +288,14 @@ pw_status check_pair(pw_ctx* ckq, const pw_ctx* ck) {
 pw_status transform_dv(pw_ctx* c, const double* dv_host, cd* dvt, cd* tmp, hipStream_t st) {
   const int n1 = c->fft[0], n2 = c->fft[1], n3 = c->fft[2];
   const long nr = (long)n1 * n2 * n3;
-  RHIP(c, hipMemcpyAsync(tmp, dv_host, sizeof(cd) * nr, hipMemcpyHostToDevice, st));
+  MKPW_HIP(c, hipMemcpyAsync(tmp, dv_host, sizeof(cd) * nr, hipMemcpyHostToDevice, st));
   const dim3 grid((unsigned)((nr + 255) / 256));
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, tmp, dvt, n1, n2, n3, 0, -1, 1.0);
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, dvt, tmp, n1, n2, n3, 1, -1, 1.0);
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, tmp, dvt, n1, n2, n3, 2, -1, 1.0 / (double)nr);
-  RTRY(check_launch(c, "mesh_dft", st));
+  MKPW_TRY(check_launch(c, "mesh_dft", st));
   // the host array must stay readable until the copy has run
-  RHIP(c, hipStreamSynchronize(st));
+  MKPW_HIP(c, hipStreamSynchronize(st));
   return PW_OK;
 }
 
@@ -338,37 +306,37 @@ pw_status transform_dv(pw_ctx* c, const double* dv_host, cd* dvt, cd* tmp, hipSt
 extern "C" pw_status pw_dfpt_rhs(pw_ctx* ckq, const pw_ctx* ck, int nocc, const void* dv_r, const void* psi_k,
                                  const void* psi_occ_kq, void* rhs) {
   using namespace mkpw;
-  RTRY(check_pair(ckq, ck));
+  MKPW_TRY(check_pair(ckq, ck));
   if (!dv_r || !psi_k || !psi_occ_kq || !rhs) return set_err(ckq, PW_EINVAL, "null argument");
   if (nocc < 1 || nocc > 64) return set_err(ckq, PW_EINVAL, "nocc must be in [1, 64]");
   (void)hipSetDevice(ckq->device);
   hipStream_t st = ckq->stream;
   const int nk = ckq->nk;
   const long nr = (long)ckq->fft[0] * ckq->fft[1] * ckq->fft[2];
-  Buf3 b(ckq);
+  DevBufs b(ckq);
   cd *dvt, *tmp, *W;
-  RTRY(b.get((size_t)nr, &dvt));
-  RTRY(b.get((size_t)nr, &tmp));
-  RTRY(b.get((size_t)nk * nocc * nocc, &W));
-  RTRY(transform_dv(ckq, (const double*)dv_r, dvt, tmp, st));
+  MKPW_TRY(b.get((size_t)nr, &dvt));
+  MKPW_TRY(b.get((size_t)nr, &tmp));
+  MKPW_TRY(b.get((size_t)nk * nocc * nocc, &W));
+  MKPW_TRY(transform_dv(ckq, (const double*)dv_r, dvt, tmp, st));
   // rhs0 = -dV u (on the k+q sphere)
   {
     const dim3 grid((unsigned)((ckq->npwx + kVT - 1) / kVT), (unsigned)nk);
     hipLaunchKernelGGL(dvpsi_kernel, grid, dim3(kVT), 0, st, dvt, ckq->fft[0], ckq->fft[1], ckq->fft[2], ck->d_npw,
                        ck->d_mkey, ck->npwx, (const cd*)psi_k, ckq->d_npw, ckq->d_mkey, ckq->npwx, (cd*)rhs, nocc,
                        -1.0);
-    RTRY(check_launch(ckq, "dvpsi", st));
+    MKPW_TRY(check_launch(ckq, "dvpsi", st));
   }
   // rhs = rhs0 - S U (U^H rhs0)  =  -(1 - S P_v) dV u
   const cd* U = (const cd*)psi_occ_kq;
   const cd* P = U;
   if (ckq->have_q) {
     cd* SU;
-    RTRY(b.get((size_t)nk * nocc * ckq->npwx, &SU));
+    MKPW_TRY(b.get((size_t)nk * nocc * ckq->npwx, &SU));
     VecSel sel;
     sel.nvec = nocc;
     sel.kstride = (long)nocc * ckq->npwx;
-    RTRY(launch_spsi(ckq, PW_FP64, sel, U, SU, nullptr, 0.0, st));
+    MKPW_TRY(launch_spsi(ckq, PW_FP64, sel, U, SU, nullptr, 0.0, st));
     P = SU;
   }
   GramArgs g;
@@ -376,21 +344,21 @@ extern "C" pw_status pw_dfpt_rhs(pw_ctx* ckq, const pw_ctx* ck, int nocc, const 
   g.B = (const cd*)rhs; g.b_kstride = (long)nocc * ckq->npwx; g.b_n = nocc;
   g.ld = ckq->npwx; g.npw = ckq->d_npw;
   g.C = W; g.c_kstride = (long)nocc * nocc; g.ldc = nocc;
-  RTRY(launch_gram(ckq, g, nocc, nocc, st));
+  MKPW_TRY(launch_gram(ckq, g, nocc, nocc, st));
   CombArgs m;
   m.X = P; m.x_kstride = (long)nocc * ckq->npwx; m.x_n = nocc;
   m.Y = (cd*)rhs; m.y_kstride = (long)nocc * ckq->npwx; m.y_n = nocc;
   m.ld = ckq->npwx; m.Cm = W; m.c_kstride = (long)nocc * nocc; m.ldc = nocc;
   m.alpha = -1.0; m.accumulate = 1;
-  RTRY(launch_combine(ckq, m, nocc, st));
-  RHIP(ckq, hipStreamSynchronize(st));
+  MKPW_TRY(launch_combine(ckq, m, nocc, st));
+  MKPW_HIP(ckq, hipStreamSynchronize(st));
   return PW_OK;
 }
 
 extern "C" pw_status pw_drho(pw_ctx* ckq, const pw_ctx* ck, int nbnd, const double* wk, const void* psi_k,
                              const void* dpsi_kq, void* drho_r) {
   using namespace mkpw;
-  RTRY(check_pair(ckq, ck));
+  MKPW_TRY(check_pair(ckq, ck));
   if (!wk || !psi_k || !dpsi_kq || !drho_r) return set_err(ckq, PW_EINVAL, "null argument");
   if (nbnd < 1 || nbnd > 1024) return set_err(ckq, PW_EINVAL, "nbnd must be in [1, 1024]");
   (void)hipSetDevice(ckq->device);
@@ -424,27 +392,27 @@ extern "C" pw_status pw_drho(pw_ctx* ckq, const pw_ctx* ck, int nbnd, const doub
   const size_t per_x = 2 * sizeof(double) * (size_t)D[1] * D[2];
   if (per_x + tiles + 2 * sizeof(double) > lds_max) return set_err(ckq, PW_EINVAL, "drho: plane-wave spheres too large for the bins");
   const int nx = (int)std::min<size_t>(D[0], (lds_max - tiles - 2 * sizeof(double)) / per_x);
-  Buf3 b(ckq);
+  DevBufs b(ckq);
   cd *part, *F, *tmp, *Fc;
   int* d_org;
   double* d_w;
   const int nchunk = std::min(nk, 64);
-  RTRY(b.get((size_t)nk * D[0] * D[1] * D[2], &part));
-  RTRY(b.get((size_t)nchunk * nr, &Fc));
-  RTRY(b.get((size_t)nr, &F));
-  RTRY(b.get((size_t)nr, &tmp));
-  RTRY(b.get((size_t)3 * nk, &d_org));
-  RTRY(b.get((size_t)nk, &d_w));
-  RHIP(ckq, hipMemcpyAsync(d_org, org.data(), sizeof(int) * org.size(), hipMemcpyHostToDevice, st));
-  RHIP(ckq, hipMemcpyAsync(d_w, wk, sizeof(double) * nk, hipMemcpyHostToDevice, st));
+  MKPW_TRY(b.get((size_t)nk * D[0] * D[1] * D[2], &part));
+  MKPW_TRY(b.get((size_t)nchunk * nr, &Fc));
+  MKPW_TRY(b.get((size_t)nr, &F));
+  MKPW_TRY(b.get((size_t)nr, &tmp));
+  MKPW_TRY(b.get((size_t)3 * nk, &d_org));
+  MKPW_TRY(b.get((size_t)nk, &d_w));
+  MKPW_HIP(ckq, hipMemcpyAsync(d_org, org.data(), sizeof(int) * org.size(), hipMemcpyHostToDevice, st));
+  MKPW_HIP(ckq, hipMemcpyAsync(d_w, wk, sizeof(double) * nk, hipMemcpyHostToDevice, st));
   for (int x0 = 0; x0 < D[0]; x0 += nx) {
     const int nxx = std::min(nx, D[0] - x0);
     const size_t lds = per_x * nxx + tiles + 2 * sizeof(double);
-    RTRY(ensure_lds_limit(ckq, (const void*)drho_pairs_kernel, lds));
+    MKPW_TRY(ensure_lds_limit(ckq, (const void*)drho_pairs_kernel, lds));
     hipLaunchKernelGGL(drho_pairs_kernel, dim3((unsigned)nk), dim3(256), lds, st, nbnd, d_w, ck->d_npw, ck->d_mkey,
                        ck->npwx, (const cd*)psi_k, ckq->d_npw, ckq->d_mkey, ckq->npwx, (const cd*)dpsi_kq, d_org,
                        D[0], D[1], D[2], x0, nxx, part);
-    RTRY(check_launch(ckq, "drho_pairs", st));
+    MKPW_TRY(check_launch(ckq, "drho_pairs", st));
   }
   const dim3 grid((unsigned)((nr + 255) / 256));
   hipLaunchKernelGGL(drho_reduce_kernel, dim3(grid.x, (unsigned)nchunk), dim3(256), 0, st, part, d_org, nk, nchunk,
@@ -454,7 +422,7 @@ extern "C" pw_status pw_drho(pw_ctx* ckq, const pw_ctx* ck, int nbnd, const doub
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, F, tmp, n1, n2, n3, 0, 1, 1.0);
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, tmp, F, n1, n2, n3, 1, 1, 1.0);
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, F, (cd*)drho_r, n1, n2, n3, 2, 1, 1.0);
-  RTRY(check_launch(ckq, "drho", st));
-  RHIP(ckq, hipStreamSynchronize(st));
+  MKPW_TRY(check_launch(ckq, "drho", st));
+  MKPW_HIP(ckq, hipStreamSynchronize(st));
   return PW_OK;
 }
