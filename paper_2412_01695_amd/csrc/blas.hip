@@ -38,18 +38,31 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a) {
   const int tid = threadIdx.x;
   const int ti = tid / kGT, tj = tid % kGT;
   double sr = 0.0, si = 0.0;
-  for (int g0 = 0; g0 < npw; g0 += kGK) {
-    for (int e = tid; e < kGT * kGK; e += 256) {
-      int r = e / kGK, g = e % kGK;
-      c64d va = {0.0, 0.0}, vb = {0.0, 0.0};
+  // each work-item stages kGT * kGK / 256 = 2 elements of each tile; the next
+  // chunk's elements are loaded into registers while the current one is used
+  constexpr int kPer = kGT * kGK / 256;
+  c64d na[kPer], nb[kPer];
+  auto fetch = [&](int g0) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * 256, r = e / kGK, g = e % kGK;
+      na[q] = nb[q] = c64d{0.0, 0.0};
       if (g0 + g < npw) {
-        if (i0 + r < ni) va = A[(long)(i0 + r) * a.ld + g0 + g];
-        if (j0 + r < nj) vb = B[(long)(j0 + r) * a.ld + g0 + g];
+        if (i0 + r < ni) na[q] = A[(long)(i0 + r) * a.ld + g0 + g];
+        if (j0 + r < nj) nb[q] = B[(long)(j0 + r) * a.ld + g0 + g];
       }
-      As[r][g] = va;
-      Bs[r][g] = vb;
+    }
+  };
+  fetch(0);
+  for (int g0 = 0; g0 < npw; g0 += kGK) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * 256, r = e / kGK, g = e % kGK;
+      As[r][g] = na[q];
+      Bs[r][g] = nb[q];
     }
     __syncthreads();
+    if (g0 + kGK < npw) fetch(g0 + kGK);
 #pragma unroll 8
     for (int g = 0; g < kGK; ++g) {
       c64d x = As[ti][g], y = Bs[tj][g];
