@@ -77,7 +77,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             sys.stderr.write(f"--- {src}\n{out}\n")
         raise RuntimeError("libmkpw build failed")
     tmp = LIB + ".tmp"
-    link = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    link = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(link, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if r.returncode != 0:
         sys.stderr.write(r.stdout.decode(errors="replace"))

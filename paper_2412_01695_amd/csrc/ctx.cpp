@@ -19,6 +19,7 @@
 #include <new>
 #include <unordered_map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -352,8 +353,10 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
     int m[3];
   };
   std::vector<std::vector<PW>> all(nk);
-  int npwmax = 0;
-  for (int ik = 0; ik < nk; ++ik) {
+  // spheres of the k-points built and sorted in parallel host threads, each
+  // over its own range of k
+  auto build_range = [&](int k0, int k1) {
+  for (int ik = k0; ik < k1; ++ik) {
     const double* kk = k + 3 * ik;
     int lo[3], hi[3];
     for (int i = 0; i < 3; ++i) {
@@ -377,8 +380,18 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
       if (x.q2 != y.q2) return x.q2 < y.q2;
       return std::lexicographical_compare(x.m, x.m + 3, y.m, y.m + 3);
     });
-    npwmax = std::max<int>(npwmax, (int)v.size());
   }
+  };
+  {
+    const int hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = std::max(1, std::min({hw, 16, nk / 16}));
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(build_range, (int)((long)nk * t / nt), (int)((long)nk * (t + 1) / nt));
+    build_range(0, (int)((long)nk / nt));
+    for (auto& x : th) x.join();
+  }
+  int npwmax = 0;
+  for (int ik = 0; ik < nk; ++ik) npwmax = std::max<int>(npwmax, (int)all[ik].size());
   if (npwmax == 0) return set_err(c, PW_EINVAL, "empty plane-wave basis");
   const int npwx = (npwmax + 63) / 64 * 64;
 

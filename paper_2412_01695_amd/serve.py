@@ -178,11 +178,15 @@ class Server:
             # projector values at every k+G of the library's order, all k at once
             mall = mkpw.pw_get_miller_all(ctx, npw)
             kidx = np.repeat(np.arange(cfg.nk), npw)
-            gidx = np.arange(mall.shape[0]) - np.repeat(np.cumsum(npw) - npw, npw)
             q = cfg.kpts[kidx] + mall.astype(np.float64) @ synth.reciprocal_rows(cfg.lat)
-            beta = np.zeros((cfg.nk, npwx, cfg.nproj), dtype=np.complex128)
-            beta[kidx, gidx, :] = synth.beta_values(cfg, q).T
-            beta = np.ascontiguousarray(beta.transpose(0, 2, 1))
+            bv = synth.beta_values(cfg, q)                     # (nproj, sum npw)
+            # (nk, nproj, npwx) with zero padding: each k's rows are a contiguous
+            # run of the concatenated plane waves
+            beta = np.zeros((cfg.nk, cfg.nproj, npwx), dtype=np.complex128)
+            flat = (kidx * (cfg.nproj * npwx) + (np.arange(mall.shape[0]) - np.repeat(np.cumsum(npw) - npw, npw)))
+            bf = beta.reshape(-1)
+            for p in range(cfg.nproj):
+                bf[flat + p * npwx] = bv[p]
             mkpw.pw_set_projectors(ctx, beta, cfg.dij)
             t1 = time.monotonic()
             with torch.cuda.stream(stream):
