@@ -168,6 +168,23 @@ int smooth235(int n) {
   }
 }
 
+// projector rows as uploaded: zero the padding (g >= npw[k]) so kernels may
+// read whole rows, and form the complex64 copy
+__global__ void prepare_beta_kernel(double* b64, float* b32, const int* npw, int nproj, int npwx, long nrows) {
+  const long total = nrows * npwx;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long row = e / npwx;
+    const int g = (int)(e - row * npwx), k = (int)(row / nproj);
+    double re = b64[2 * e], im = b64[2 * e + 1];
+    if (g >= npw[k]) {
+      re = im = 0.0;
+      b64[2 * e] = b64[2 * e + 1] = 0.0;
+    }
+    b32[2 * e] = (float)re;
+    b32[2 * e + 1] = (float)im;
+  }
+}
+
 template <class T>
 pw_status upload(pw_ctx* c, const T* host, size_t count, T** dev) {
   void* p = nullptr;
@@ -570,28 +587,21 @@ pw_status pw_set_projectors(pw_ctx* c, int nproj, const void* beta, const void* 
   c->have_proj = false;
   c->nproj = 0;
   if (nproj > 0) {
-    // zero the padding rows so kernels may read whole rows
-    std::vector<double> b64(2 * nb, 0.0);
-    std::vector<float> b32(2 * nb, 0.0f);
-    for (int ik = 0; ik < c->nk; ++ik)
-      for (int p = 0; p < nproj; ++p) {
-        size_t row = ((size_t)ik * nproj + p) * c->npwx;
-        for (int g = 0; g < c->npw[ik]; ++g) {
-          b64[2 * (row + g)] = bsrc[2 * (row + g)];
-          b64[2 * (row + g) + 1] = bsrc[2 * (row + g) + 1];
-          b32[2 * (row + g)] = (float)b64[2 * (row + g)];
-          b32[2 * (row + g) + 1] = (float)b64[2 * (row + g) + 1];
-        }
-      }
+    // rows uploaded as given; the padding is zeroed and the complex64 copy
+    // formed on the device
     std::vector<float> d32(2 * (size_t)nproj * nproj);
     for (size_t i = 0; i < d32.size(); ++i) d32[i] = (float)d[i];
     pw_status s;
     double* p64 = nullptr;
     float* p32 = nullptr;
-    if ((s = upload(c, b64.data(), b64.size(), &p64)) != PW_OK) return s;
+    if ((s = upload(c, bsrc, 2 * nb, &p64)) != PW_OK) return s;
     c->d_beta64 = p64;
-    if ((s = upload(c, b32.data(), b32.size(), &p32)) != PW_OK) return s;
-    c->d_beta32 = p32;
+    void* v32 = nullptr;
+    if ((s = dev_alloc(c, 2 * nb * sizeof(float), &v32)) != PW_OK) return s;
+    c->d_beta32 = v32;
+    hipLaunchKernelGGL(prepare_beta_kernel, dim3(1024), dim3(256), 0, c->stream, p64, (float*)v32, c->d_npw, nproj,
+                       c->npwx, (long)c->nk * nproj);
+    HIPCHK(c, hipGetLastError());
     if ((s = upload(c, d, 2 * (size_t)nproj * nproj, &p64)) != PW_OK) return s;
     c->d_dij64 = p64;
     if ((s = upload(c, d32.data(), d32.size(), &p32)) != PW_OK) return s;
