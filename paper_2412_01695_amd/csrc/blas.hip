@@ -144,17 +144,26 @@ __global__ __launch_bounds__(256) void rows_trmm_kernel(c64d* Yb, long y_kstride
   for (int e = threadIdx.x; e < n * n; e += 256) ms[e] = M[(long)(e / n) * ldm + (e % n)];
   __syncthreads();
   if (g >= npwx) return;
-  // descending j: Y_j only needs Y_i, i <= j, which are not yet overwritten
-  for (int j = n - 1; j >= 0; --j) {
-    double ar = 0.0, ai = 0.0;
-    for (int i = 0; i <= j; ++i) {
-      c64d x = Y[(long)i * npwx + g];
-      c64d c = ms[i * n + j];
-      ar += x.x * c.x - x.y * c.y;
-      ai += x.x * c.y + x.y * c.x;
+  // each row of this work-item's column is read once and added into the
+  // outputs it feeds (Y_j = sum_{i <= j} Y_i M_ij, outputs in registers)
+  constexpr int kMax = 32;
+  double ar[kMax], ai[kMax];
+#pragma unroll
+  for (int j = 0; j < kMax; ++j) ar[j] = ai[j] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const c64d x = Y[(long)i * npwx + g];
+#pragma unroll
+    for (int j = 0; j < kMax; ++j) {
+      if (j >= i && j < n) {
+        const c64d c = ms[i * n + j];
+        ar[j] += x.x * c.x - x.y * c.y;
+        ai[j] += x.x * c.y + x.y * c.x;
+      }
     }
-    Y[(long)j * npwx + g] = {ar, ai};
   }
+#pragma unroll
+  for (int j = 0; j < kMax; ++j)
+    if (j < n) Y[(long)j * npwx + g] = {ar[j], ai[j]};
 }
 
 // ------------------------------------------------------------------ precision conversion of row blocks

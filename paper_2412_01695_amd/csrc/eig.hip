@@ -11,12 +11,14 @@
 //      w = p - (g/2)(u^H p) u; the u_j stay below the diagonal;
 //   2. a diagonal phase change D (d_0 = 1, d_{j+1} = d_j e_j / |e_j|) making
 //      T = D T_r D^H with T_r real symmetric, off-diagonal |e_j|;
-//   3. eigenvalues of T_r by bisection on Sturm counts (one lane each);
+//   3. eigenvalues of T_r by multisection on Sturm counts (16 points per step,
+//      eight lanes per eigenvalue);
 //   4. eigenvectors of T_r by inverse iteration, Gaussian elimination with
 //      partial pivoting on T_r - lambda (one lane each, from a fixed
 //      pseudo-random start), then Gram-Schmidt (twice) within each cluster of
 //      eigenvalues closer than 1e-3 of the matrix norm;
-//   5. back through D and the reflectors: x = H_0 (... H_{n-3} (D y)).
+//   5. back through D and the reflectors: x = H_0 (... H_{n-3} (D y)), eight
+//      eigenvectors per wave at once.
 // About (4/3) n^3 complex multiply-adds, against roughly 30 n^3 for the cyclic
 // Jacobi sweeps this replaces.
 //
@@ -232,31 +234,41 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
   }
   __syncthreads();
 
-  // ---- 3. eigenvalues of T_r: four work-items per eigenvalue; each step
-  //         counts the eigenvalues below four interior points of the bracket
-  //         (Sturm sequence) and keeps the fifth of it that holds eigenvalue t
+  // ---- 3. eigenvalues of T_r: eight work-items per eigenvalue, two points
+  //         each; every step counts the eigenvalues below 16 interior points of
+  //         the bracket (Sturm sequences, the two of a work-item interleaved)
+  //         and keeps the seventeenth of it that holds eigenvalue t
   {
-    const int t = tid >> 2, sub = tid & 3;
-    if (t < nev) {  // whole quads
+    const int t = tid >> 3, sub = tid & 7;
+    if (t < nev) {  // whole groups of eight
       const double pivmin = S.scal[3];
       double lo = S.scal[0], hi = S.scal[1];
       for (int it = 0; it < 100; ++it) {
         if (!(hi - lo > 4.5e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
-        const double x = lo + (hi - lo) * (0.2 * (sub + 1));
-        int cnt = 0;
-        double q = S.d[0] - x;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
+        const double xa = lo + (hi - lo) * ((2 * sub + 1) / 17.0);
+        const double xb = lo + (hi - lo) * ((2 * sub + 2) / 17.0);
+        int ca = 0, cb = 0;
+        double qa = S.d[0] - xa, qb = S.d[0] - xb;
+        if (fabs(qa) < pivmin) qa = -pivmin;
+        if (fabs(qb) < pivmin) qb = -pivmin;
+        ca += qa < 0.0;
+        cb += qb < 0.0;
         for (int i = 1; i < n; ++i) {
-          q = (S.d[i] - x) - S.e[i - 1] * S.e[i - 1] * rcp_nr(q);
-          if (fabs(q) < pivmin) q = -pivmin;
-          cnt += q < 0.0;
+          const double di = S.d[i], e2 = S.e[i - 1] * S.e[i - 1];
+          qa = (di - xa) - e2 * rcp_nr(qa);
+          qb = (di - xb) - e2 * rcp_nr(qb);
+          if (fabs(qa) < pivmin) qa = -pivmin;
+          if (fabs(qb) < pivmin) qb = -pivmin;
+          ca += qa < 0.0;
+          cb += qb < 0.0;
         }
-        double lc = cnt <= t ? x : lo, hc = cnt > t ? x : hi;
-        lc = fmax(lc, __shfl_xor(lc, 1, 64));
-        lc = fmax(lc, __shfl_xor(lc, 2, 64));
-        hc = fmin(hc, __shfl_xor(hc, 1, 64));
-        hc = fmin(hc, __shfl_xor(hc, 2, 64));
+        double lc = lo, hc = hi;
+        if (ca <= t) lc = xa; else hc = fmin(hc, xa);
+        if (cb <= t) lc = fmax(lc, xb); else hc = fmin(hc, xb);
+        for (int o = 1; o < 8; o <<= 1) {
+          lc = fmax(lc, __shfl_xor(lc, o, 64));
+          hc = fmin(hc, __shfl_xor(hc, o, 64));
+        }
         if (lc == lo && hc == hi) break;  // the points no longer split the bracket
         lo = lc;
         hi = hc;
@@ -358,25 +370,42 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
   }
   __syncthreads();
 
-  // ---- 5. x = H_0 (... H_{n-3} (D y)): wave v takes eigenpairs v, v + 4, ...,
-  //         lane i holds component i
-  for (int t = wave; t < nev; t += 4) {
-    cd* z = S.Z + t * kEigLd;
-    const double yv = lane < n ? S.Y[t * kEigMax + lane] : 0.0;
-    cd zi = {0.0, 0.0};
-    if (lane < n) zi = {S.ph[lane].x * yv, S.ph[lane].y * yv};
+  // ---- 5. x = H_0 (... H_{n-3} (D y)): wave v takes eigenpairs v, v + 4, ...
+  //         (at most eight), all of them together so that their lane sums are
+  //         independent and overlap; lane i holds component i
+  {
+    constexpr int kPerWave = kEigNev / 4;
+    cd zi[kPerWave];
+#pragma unroll
+    for (int s2 = 0; s2 < kPerWave; ++s2) {
+      const int t = wave + 4 * s2;
+      const double yv = (t < nev && lane < n) ? S.Y[t * kEigMax + lane] : 0.0;
+      zi[s2] = lane < n ? cd{S.ph[lane].x * yv, S.ph[lane].y * yv} : cd{0.0, 0.0};
+    }
     for (int j = n - 3; j >= 0; --j) {
       const double gj = S.g[j];
       if (gj == 0.0) continue;
       cd u = {0.0, 0.0};
       if (lane > j && lane < n) u = A[lane * kEigLd + j];
-      // c = g u^H z
-      const double cr = gj * wave_sum64(u.x * zi.x + u.y * zi.y);
-      const double ci = gj * wave_sum64(u.x * zi.y - u.y * zi.x);
-      zi.x -= cr * u.x - ci * u.y;
-      zi.y -= cr * u.y + ci * u.x;
+      double cr[kPerWave], ci[kPerWave];
+#pragma unroll
+      for (int s2 = 0; s2 < kPerWave; ++s2) {
+        // c = g u^H z
+        cr[s2] = wave_sum64(u.x * zi[s2].x + u.y * zi[s2].y);
+        ci[s2] = wave_sum64(u.x * zi[s2].y - u.y * zi[s2].x);
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < kPerWave; ++s2) {
+        const double a = gj * cr[s2], b = gj * ci[s2];
+        zi[s2].x -= a * u.x - b * u.y;
+        zi[s2].y -= a * u.y + b * u.x;
+      }
     }
-    if (lane < n) z[lane] = zi;
+#pragma unroll
+    for (int s2 = 0; s2 < kPerWave; ++s2) {
+      const int t = wave + 4 * s2;
+      if (t < nev && lane < n) S.Z[t * kEigLd + lane] = zi[s2];
+    }
   }
   __syncthreads();
   if (tid < nev) w[(long)k * nev_req + tid] = S.lam[tid];
