@@ -17,7 +17,7 @@
 //      partial pivoting on T_r - lambda (one lane each, from a fixed
 //      pseudo-random start), then Gram-Schmidt (twice) within each cluster of
 //      eigenvalues closer than 1e-3 of the matrix norm;
-//   5. back through D and the reflectors: x = H_0 (... H_{n-3} (D y)), eight
+//   5. back through D and the reflectors: x = H_0 (... H_{n-3} (D y)), four
 //      eigenvectors per wave at once.
 // About (4/3) n^3 complex multiply-adds, against roughly 30 n^3 for the cyclic
 // Jacobi sweeps this replaces.
@@ -38,6 +38,9 @@ using cd = cplx<double>;
 constexpr int kEigMax = 64;   // largest reduced problem
 constexpr int kEigLd = kEigMax + 1;
 constexpr int kEigNev = 32;   // most eigenpairs returned
+constexpr int kEigThreads = 512;             // one workgroup per k-point
+constexpr int kEigWaves = kEigThreads / 64;
+constexpr int kEigPQ = kEigThreads / 64;     // work-items per row of p = g A u
 
 __device__ __forceinline__ double wave_sum64(double v) { return wave_sum(v); }
 
@@ -89,7 +92,7 @@ struct EigLds {
   double scal[4];
 };
 
-__global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, long a_kstride, int lda,
+__global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict__ Ag, long a_kstride, int lda,
                                                     const int* __restrict__ nk_arr, int nev_req,
                                                     double* __restrict__ w, cd* __restrict__ Vg, long v_kstride,
                                                     int ldv) {
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
   cd* A = S.A;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const cd* Ak = Ag + (long)k * a_kstride;
-  for (int e = tid; e < n * n; e += 256) {
+  for (int e = tid; e < n * n; e += kEigThreads) {
     const int i = e / n, j = e - (e / n) * n;
     const cd a = Ak[(long)i * lda + j], b = Ak[(long)j * lda + i];  // exact Hermitian part
     A[i * kEigLd + j] = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
@@ -131,20 +134,21 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
     const double gj = S.g[j];  // uniform
     if (gj != 0.0) {
       // p_r = g sum_l A[j+1+r][j+1+l] u_l, four work-items per row
-      const int r = tid >> 2, q = tid & 3;
+      const int r = tid / kEigPQ, q = tid % kEigPQ;
       cd acc = {0.0, 0.0};
       if (r < m) {
         const int i = j + 1 + r;
-        for (int l = q; l < m; l += 4) {
+        for (int l = q; l < m; l += kEigPQ) {
           const cd a = A[i * kEigLd + j + 1 + l], u = A[(j + 1 + l) * kEigLd + j];
           acc.x += a.x * u.x - a.y * u.y;
           acc.y += a.x * u.y + a.y * u.x;
         }
       }
-      acc.x += __shfl_xor(acc.x, 1, 64);
-      acc.y += __shfl_xor(acc.y, 1, 64);
-      acc.x += __shfl_xor(acc.x, 2, 64);
-      acc.y += __shfl_xor(acc.y, 2, 64);
+#pragma unroll
+      for (int o = 1; o < kEigPQ; o <<= 1) {
+        acc.x += __shfl_xor(acc.x, o, 64);
+        acc.y += __shfl_xor(acc.y, o, 64);
+      }
       if (r < m && q == 0) S.pw[r] = {gj * acc.x, gj * acc.y};
     }
     __syncthreads();
@@ -190,7 +194,7 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
     if (gj != 0.0) {
       // the rest of the trailing block (columns j+2 ..): A -= u w^H + w u^H
       const int mc = m - 1;
-      for (int e = tid; e < m * mc; e += 256) {
+      for (int e = tid; e < m * mc; e += kEigThreads) {
         const int r = e / mc, l = 1 + e - (e / mc) * mc;
         const cd ur = A[(j + 1 + r) * kEigLd + j], ul = A[(j + 1 + l) * kEigLd + j];
         const cd pr = S.pw[r], pl = S.pw[l];
@@ -370,15 +374,15 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
   }
   __syncthreads();
 
-  // ---- 5. x = H_0 (... H_{n-3} (D y)): wave v takes eigenpairs v, v + 4, ...
-  //         (at most eight), all of them together so that their lane sums are
+  // ---- 5. x = H_0 (... H_{n-3} (D y)): wave v takes eigenpairs v, v + 8, ...
+  //         (at most four), all of them together so that their lane sums are
   //         independent and overlap; lane i holds component i
   {
-    constexpr int kPerWave = kEigNev / 4;
+    constexpr int kPerWave = kEigNev / kEigWaves;
     cd zi[kPerWave];
 #pragma unroll
     for (int s2 = 0; s2 < kPerWave; ++s2) {
-      const int t = wave + 4 * s2;
+      const int t = wave + kEigWaves * s2;
       const double yv = (t < nev && lane < n) ? S.Y[t * kEigMax + lane] : 0.0;
       zi[s2] = lane < n ? cd{S.ph[lane].x * yv, S.ph[lane].y * yv} : cd{0.0, 0.0};
     }
@@ -403,14 +407,14 @@ __global__ __launch_bounds__(256) void heevx_kernel(const cd* __restrict__ Ag, l
     }
 #pragma unroll
     for (int s2 = 0; s2 < kPerWave; ++s2) {
-      const int t = wave + 4 * s2;
+      const int t = wave + kEigWaves * s2;
       if (t < nev && lane < n) S.Z[t * kEigLd + lane] = zi[s2];
     }
   }
   __syncthreads();
   if (tid < nev) w[(long)k * nev_req + tid] = S.lam[tid];
   cd* Vk = Vg + (long)k * v_kstride;
-  for (int e = tid; e < n * nev; e += 256) {
+  for (int e = tid; e < n * nev; e += kEigThreads) {
     const int r = e / nev, t = e - (e / nev) * nev;
     Vk[(long)r * ldv + t] = S.Z[t * kEigLd + r];
   }
@@ -494,7 +498,7 @@ pw_status launch_heev(pw_ctx* c, const cd* A, long a_kstride, int lda, const int
     pw_status s = ensure_lds_limit(c, (const void*)heevx_kernel, lds);
     if (s != PW_OK) return s;
   }
-  hipLaunchKernelGGL(heevx_kernel, dim3(c->nk), dim3(256), lds, st, A, a_kstride, lda, n, nev, w, V, v_kstride, ldv);
+  hipLaunchKernelGGL(heevx_kernel, dim3(c->nk), dim3(kEigThreads), lds, st, A, a_kstride, lda, n, nev, w, V, v_kstride, ldv);
   return check_launch(c, "heevx", st);
 }
 
