@@ -252,39 +252,65 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     return check_launch(c, "init_resid", st);
   };
 
-  std::vector<int> act(nsys, 1), iters(nsys, 0);
+  // The host reads the active flags one step late: the flags of step it are
+  // copied to page-locked memory behind step1 and looked at once step it + 1
+  // is queued, so the device never waits for the host between steps.  A step
+  // queued after every system has converged changes nothing (both step
+  // kernels skip inactive systems, and t is scratch).
+  HostStage hs(c, st);
+  MKPW_TRY(hs.init(0, 2 * sizeof(int) * nsys));
+  int* slot[2] = {hs.back<int>(0), hs.back<int>(sizeof(int) * nsys)};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  struct Events {
+    hipEvent_t* e;
+    ~Events() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } ev_guard{ev};
+  for (int i = 0; i < 2; ++i) MKPW_HIP(c, hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+
+  std::vector<int> iters(nsys, 0);
   MKPW_TRY(restart());
   int first = 1;
   bool ok = false;
   int it_total = 0;
-  for (int it = 1; it <= max_iter; ++it) {
-    // the FP32 phase of the mixed mode stops at a residual reduction its
-    // H application can still resolve; the FP64 phase runs to thr
-    const double rel = fp64_h ? 0.0 : kRelFp32;
-    hipLaunchKernelGGL(step1_kernel, dim3((unsigned)nsys), dim3(256), 0, st, r, d, dold, c->d_kin, tk, c->d_npw,
-                       npwx, nrhs, rho, rho_old, rho0, active, first, thr, rel);
-    MKPW_TRY(check_launch(c, "cg_step1", st));
-    MKPW_HIP(c, hipMemcpyAsync(act.data(), active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
-    MKPW_HIP(c, hipStreamSynchronize(st));
-    long n_act = 0;
-    for (long s = 0; s < nsys; ++s)
-      if (act[s]) {
-        ++n_act;
-        iters[s] = it_total + it;
-      }
-    if (n_act == 0) {
-      if (!fp64_h) {
-        // FP64 refinement: true residual with H in FP64, then continue
-        fp64_h = true;
-        it_total += it;
-        first = 1;
-        MKPW_TRY(restart());
-        it = 0;
-        continue;
-      }
-      ok = true;
-      break;
+  for (int it = 1;; ++it) {
+    if (it <= max_iter) {
+      // the FP32 phase of the mixed mode stops at a residual reduction its
+      // H application can still resolve; the FP64 phase runs to thr
+      const double rel = fp64_h ? 0.0 : kRelFp32;
+      hipLaunchKernelGGL(step1_kernel, dim3((unsigned)nsys), dim3(256), 0, st, r, d, dold, c->d_kin, tk, c->d_npw,
+                         npwx, nrhs, rho, rho_old, rho0, active, first, thr, rel);
+      MKPW_TRY(check_launch(c, "cg_step1", st));
+      MKPW_HIP(c, hipMemcpyAsync(slot[it & 1], active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
+      MKPW_HIP(c, hipEventRecord(ev[it & 1], st));
     }
+    if (it > 1) {
+      // the flags after step1 of step it - 1
+      MKPW_HIP(c, hipEventSynchronize(ev[(it - 1) & 1]));
+      const int* act = slot[(it - 1) & 1];
+      long n_act = 0;
+      for (long s = 0; s < nsys; ++s)
+        if (act[s]) {
+          ++n_act;
+          iters[s] = it_total + it - 1;
+        }
+      if (n_act == 0) {
+        if (!fp64_h) {
+          // FP64 refinement: true residual with H in FP64, then continue
+          fp64_h = true;
+          it_total += it - 1;
+          first = 1;
+          MKPW_TRY(restart());
+          it = 0;
+          continue;
+        }
+        ok = true;
+        break;
+      }
+    }
+    if (it > max_iter) break;
     first = 0;
     MKPW_TRY(apply_a(d, active));
     hipLaunchKernelGGL(step2_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, d, dold, x, r, eps, c->d_npw, npwx,

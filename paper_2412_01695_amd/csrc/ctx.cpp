@@ -56,6 +56,26 @@ pw_status dev_alloc(pw_ctx* c, size_t bytes, void** out) {
   return PW_OK;
 }
 
+pw_status host_pinned(pw_ctx* c, size_t bytes, void** out) {
+  // copies queued by an earlier call that ended early may still read the
+  // buffer: they finish before it is reused or replaced
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && bytes > c->pin_cap) {
+    if (c->pin) (void)hipHostFree(c->pin);
+    c->pin = nullptr;
+    c->pin_cap = 0;
+    const size_t cap = std::max(bytes, (size_t)1 << 16);
+    e = hipHostMalloc(&c->pin, cap, hipHostMallocDefault);
+    if (e == hipSuccess) c->pin_cap = cap;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(c, PW_EDEVICE, std::string("page-locked staging: ") + hipGetErrorString(e));
+  }
+  *out = c->pin;
+  return PW_OK;
+}
+
 void dev_free(pw_ctx* c, void* p) {
   if (!p) return;
   for (size_t i = 0; i < c->owned.size(); ++i) {
@@ -238,6 +258,7 @@ void pw_destroy(pw_ctx* c) {
     for (auto& m : c->owned) (void)hipFreeAsync(m.p, c->stream);
     c->owned.clear();
     (void)hipStreamSynchronize(c->stream);
+    if (c->pin) (void)hipHostFree(c->pin);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;

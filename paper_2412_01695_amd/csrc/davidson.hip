@@ -242,18 +242,20 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
       rnh((size_t)nk * nbnd);
   std::vector<int> iters(nk, 0);
   std::vector<int> force_restart(nk, 0);
-  // host->device uploads read snapshots that live until the next stream
-  // synchronisation, so the host arrays may change right after a call
-  std::vector<std::vector<int>> keep;
-  auto h2d = [&](int* d, const std::vector<int>& h) {
-    keep.emplace_back(h);
-    return hipMemcpyAsync(d, keep.back().data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, st);
-  };
-  auto sync = [&]() {
-    hipError_t e = hipStreamSynchronize(st);
-    keep.clear();
-    return e;
-  };
+  // uploads go through page-locked snapshots, so the host arrays may change
+  // right after a call; the per-k read-backs land in page-locked memory too
+  // (between two synchronisations an iteration uploads at most ten (nk) arrays
+  // and two (nk, nbnd) ones)
+  const size_t nkb = (size_t)nk * nbnd;
+  HostStage hs(c, st);
+  MKPW_TRY(hs.init(sizeof(int) * (16 * (size_t)nk + 2 * nkb) + 256 * 24, sizeof(double) * 4 * nkb + sizeof(int) * nk));
+  double* p_th = hs.back<double>(0);
+  double* p_rn = p_th + nkb;
+  double* p_n0 = p_rn + nkb;
+  double* p_n1 = p_n0 + nkb;
+  int* p_info = reinterpret_cast<int*>(p_n1 + nkb);
+  auto h2d = [&](int* d, const std::vector<int>& h) { return hs.up(d, h.data(), h.size()); };
+  auto sync = [&]() { return hs.sync(); };
 
   // diagonal of H for the preconditioner
   {
@@ -347,8 +349,9 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
       MKPW_TRY(launch_chol_inv(c, Sm, (long)nbnd * nbnd, nbnd, d_nnc, Mm, (long)nbnd * nbnd, nbnd, d_info, st));
       MKPW_TRY(launch_trmm(c, V, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
       if (gen) MKPW_TRY(launch_trmm(c, SV, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
-      MKPW_HIP(c, hipMemcpyAsync(info.data(), d_info, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
+      MKPW_HIP(c, hipMemcpyAsync(p_info, d_info, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
       MKPW_HIP(c, sync());
+      std::memcpy(info.data(), p_info, sizeof(int) * nk);
       bool changed = false;
       for (int k = 0; k < nk; ++k)
         if (info[k] && nnc[k] > 0) {
@@ -371,9 +374,11 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     if (nnc_max <= 0) return PW_OK;
     MKPW_TRY(project(nb_max, nnc_max));
     if (allow_residual) {
-      MKPW_HIP(c, hipMemcpyAsync(n0h.data(), nrm0, sizeof(double) * n0h.size(), hipMemcpyDeviceToHost, st));
-      MKPW_HIP(c, hipMemcpyAsync(n1h.data(), nrm1, sizeof(double) * n1h.size(), hipMemcpyDeviceToHost, st));
+      MKPW_HIP(c, hipMemcpyAsync(p_n0, nrm0, sizeof(double) * nkb, hipMemcpyDeviceToHost, st));
+      MKPW_HIP(c, hipMemcpyAsync(p_n1, nrm1, sizeof(double) * nkb, hipMemcpyDeviceToHost, st));
       MKPW_HIP(c, sync());
+      std::memcpy(n0h.data(), p_n0, sizeof(double) * nkb);
+      std::memcpy(n1h.data(), p_n1, sizeof(double) * nkb);
       bool any = false;
       for (int k = 0; k < nk; ++k)
         for (int r = 0; r < nbnd; ++r) {
@@ -476,9 +481,11 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
                          T, Rb, rn);
       MKPW_TRY(check_launch(c, "resid", st));
     }
-    MKPW_HIP(c, hipMemcpyAsync(th.data(), theta, sizeof(double) * th.size(), hipMemcpyDeviceToHost, st));
-    MKPW_HIP(c, hipMemcpyAsync(rnh.data(), rn, sizeof(double) * rnh.size(), hipMemcpyDeviceToHost, st));
+    MKPW_HIP(c, hipMemcpyAsync(p_th, theta, sizeof(double) * nkb, hipMemcpyDeviceToHost, st));
+    MKPW_HIP(c, hipMemcpyAsync(p_rn, rn, sizeof(double) * nkb, hipMemcpyDeviceToHost, st));
     MKPW_HIP(c, sync());
+    std::memcpy(th.data(), p_th, sizeof(double) * nkb);
+    std::memcpy(rnh.data(), p_rn, sizeof(double) * nkb);
     const double etol = fp64_h ? tol : tol32, rtol = fp64_h ? rtol64 : rtol32;
     int n_active = 0, nnc_max = 0, nb_max = 0;
     for (int k = 0; k < nk; ++k) {

@@ -127,6 +127,11 @@ struct pw_ctx {
   std::vector<short> sof;       // nk * wx * wy
   int wx = 0, wy = 0, wz = 0, smax = 0;
 
+  // page-locked host memory for the solvers' small per-iteration copies,
+  // grown on demand and freed with the context
+  void* pin = nullptr;
+  size_t pin_cap = 0;
+
   // device copies
   std::vector<mkpw::DevMem> owned;
   int* d_npw = nullptr;
@@ -160,6 +165,8 @@ namespace mkpw {
 pw_status set_err(pw_ctx* c, pw_status s, const std::string& msg);
 pw_status dev_alloc(pw_ctx* c, size_t bytes, void** out);
 void dev_free(pw_ctx* c, void* p);
+// c->pin with at least `bytes` (the context's stream is synchronised first)
+pw_status host_pinned(pw_ctx* c, size_t bytes, void** out);
 
 // H|psi> over the selected vectors (kernels in hpsi.hip). psi/hpsi are
 // complex double (prec = PW_FP64) or complex float (PW_MIXED).
