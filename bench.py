@@ -45,7 +45,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("hpsi_kernel.hpp", "fft.hpp", "internal.hpp", "wave.hpp")
 MEASURED_TRAFFIC = {
     ("fcc1-ecut30-fft24-512k", "fp64", (1, 256, 10)): {
-        "sources": "c1c8f49f7f7e4a7f", "fetch_kib": 36140.1, "write_kib": 51200.0,
+        "sources": "27d64d7a4f53fc64", "fetch_kib": 36140.1, "write_kib": 51200.0,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "profile": "profiles/hpsi_fp64_fcc1-ecut30-fft24-512k.md"},
 }
