@@ -25,6 +25,10 @@
  *   Every call returns a pw_status; on error pw_last_error() holds a message
  *   and the context is unchanged unless stated otherwise.  No exception
  *   crosses the ABI.
+ *   Threads: a context is used by one host thread at a time; different
+ *   contexts may be used from different threads at once.  Besides its device
+ *   memory a context keeps a small page-locked host buffer (grown to what the
+ *   solvers' per-iteration copies need), freed by pw_destroy.
  */
 #ifndef MKPW_H
 #define MKPW_H
