@@ -111,6 +111,21 @@ def test_davidson_c2_full_batch_sampled():
     assert err < TOL_FP64_HA
 
 
+def test_davidson_repeated_on_one_context():
+    # the context's page-locked staging grows between calls (4, then 8 bands on
+    # all 512 k) and is reused by a smaller call; every call matches the oracle
+    cfg = synth.make_config(2)
+    torch, s = _system(cfg)
+    ks = [0, 137, 300, cfg.nk - 1]
+    ref = _oracle_eigs(cfg, s, ks, 8)
+    for nbnd in (4, 8, 4):
+        st, eig, iters, conv, psi = _davidson(torch, s, 0, 1e-10, nbnd=nbnd)
+        assert st == 0 and conv.all()
+        err = max(np.max(np.abs(eig[ik] - ref[ik][:nbnd])) for ik in ks)
+        print("C2 nbnd", nbnd, "max |eig err| Ha", err, "iters", iters.min(), iters.max())
+        assert err < TOL_FP64_HA
+
+
 def test_davidson_free_electron_degenerate():
     # V = 0, no projectors: eigenvalues are the sorted kinetic energies, with
     # multiplets split across the band cut at some k
