@@ -159,15 +159,23 @@ def oracle_eig_error(cfg, vloc, miller_lib, eigs, nsample=8):
 
 
 def time_davidson(torch, mkpw, sysm, prec, tol_ry):
+    """Time-to-solution of one Davidson solve from the seeded guess, run twice
+    from the same start: the first solve in a process also autotunes the H|psi>
+    launch shape for each row count the solver applies H to (once per process,
+    precision, mesh and row-count bucket) and is reported as first_seconds; the
+    second is the steady state reported as seconds."""
     cfg = sysm.cfg
-    psi = torch.from_numpy(sysm.psi_guess()).cuda()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, eig, iters, conv = mkpw.pw_davidson(sysm.ctx, prec, cfg.nbnd, psi, cfg.nk, tol_ry, 300)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return {"seconds": dt, "status": int(st), "converged_k": int(conv.sum()), "iters_min": int(iters.min()),
-            "iters_max": int(iters.max()), "tol_ry": tol_ry}, eig
+    guess = torch.from_numpy(sysm.psi_guess()).cuda()
+    times = []
+    for _ in range(2):
+        psi = guess.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, eig, iters, conv = mkpw.pw_davidson(sysm.ctx, prec, cfg.nbnd, psi, cfg.nk, tol_ry, 300)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return {"seconds": times[1], "first_seconds": times[0], "status": int(st), "converged_k": int(conv.sum()),
+            "iters_min": int(iters.min()), "iters_max": int(iters.max()), "tol_ry": tol_ry}, eig
 
 
 def dfpt_sample(torch, mkpw, cfg_id, thr=1e-24):
@@ -207,19 +215,22 @@ def dfpt_sample(torch, mkpw, cfg_id, thr=1e-24):
         eps_t = torch.from_numpy(eps).cuda()[:, :, None]
         a_t = torch.from_numpy(alpha).cuda()[:, None, None]
         for name, prec in (("fp64", mkpw.PW_FP64), ("mixed", mkpw.PW_MIXED)):
-            x = torch.zeros_like(rhs)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, it = mkpw.pw_dfpt_cg(sysm.ctx, prec, nocc, u, eps, alpha, nocc, rhs, x, thr, 2000)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
+            times = []
+            for _ in range(2):  # the first also autotunes H|psi> shapes (as in time_davidson)
+                x = torch.zeros_like(rhs)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, it = mkpw.pw_dfpt_cg(sysm.ctx, prec, nocc, u, eps, alpha, nocc, rhs, x, thr, 2000)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            dt = times[1]
             hx = torch.empty_like(x)
             mkpw.pw_h_psi(sysm.ctx, mkpw.PW_FP64, nocc, x, hx)
             ux = torch.bmm(u.conj(), x.transpose(1, 2).contiguous())
             ax = hx - eps_t * x + a_t * torch.bmm(ux.transpose(1, 2).contiguous(), u)
             rel = (torch.linalg.vector_norm(ax - rhs, dim=2) / torch.linalg.vector_norm(rhs, dim=2)).max().item()
-            out[name] = {"seconds": dt, "status": int(st), "iters_min": int(it.min()), "iters_max": int(it.max()),
-                         "systems_per_s": cfg.nk * nocc / dt, "max_rel_residual": rel}
+            out[name] = {"seconds": dt, "first_seconds": times[0], "status": int(st), "iters_min": int(it.min()),
+                         "iters_max": int(it.max()), "systems_per_s": cfg.nk * nocc / dt, "max_rel_residual": rel}
         return out
     finally:
         dsys.close()
@@ -306,12 +317,17 @@ def dfpt_q_sample(torch, mkpw, cfg_id):
         eig = {}
         vec = {}
         for name, s in (("k", sk), ("k+q", sq)):
-            u = torch.from_numpy(s.psi_guess(nb)).cuda()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, e, it, conv = mkpw.pw_davidson(s.ctx, mkpw.PW_FP64, nb, u, cfg.nk, 1e-10, 300)
-            torch.cuda.synchronize()
-            out[f"davidson_{name}_s"] = time.perf_counter() - t0
+            guess = torch.from_numpy(s.psi_guess(nb)).cuda()
+            times = []
+            for _ in range(2):  # the first also autotunes H|psi> shapes (as in time_davidson)
+                u = guess.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, e, it, conv = mkpw.pw_davidson(s.ctx, mkpw.PW_FP64, nb, u, cfg.nk, 1e-10, 300)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            out[f"davidson_{name}_s"] = times[1]
+            out[f"davidson_{name}_first_s"] = times[0]
             eig[name], vec[name] = e, u
         ek, eq = eig["k"], eig["k+q"]
         gap = float(np.min(eq[:, nocc] - ek[:, nocc - 1]))
