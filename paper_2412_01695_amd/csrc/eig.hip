@@ -37,6 +37,9 @@ using cd = cplx<double>;
 
 constexpr int kEigMax = 64;   // largest reduced problem
 constexpr int kEigLd = kEigMax + 1;
+// row stride of the real per-eigenpair arrays: in the inverse iteration lane t
+// walks its own row, and the odd stride puts the lanes on different LDS banks
+constexpr int kEigYs = kEigMax + 1;
 constexpr int kEigNev = 32;   // most eigenpairs returned
 constexpr int kEigThreads = 512;             // one workgroup per k-point
 constexpr int kEigWaves = kEigThreads / 64;
@@ -77,9 +80,9 @@ __device__ __forceinline__ void make_reflector(cd x, int mm, int lane, double& g
 
 struct EigLds {
   cd A[kEigMax * kEigLd];                  // matrix, then the reflectors below the diagonal
-  double Y[kEigNev * kEigMax];             // eigenvectors of T_r, one row per eigenpair
+  double Y[kEigNev * kEigYs];              // eigenvectors of T_r, one row per eigenpair
   union {
-    double U[3 * kEigNev * kEigMax];       // per-lane elimination rows (u0, u1, u2)
+    double U[3 * kEigNev * kEigYs];        // per-lane elimination rows (u0, u1, u2)
     cd Z[kEigNev * kEigLd];                // eigenvectors of A being back-transformed
   };
   cd ecx[kEigMax];                         // complex subdiagonal of T
@@ -208,33 +211,49 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
     __syncthreads();
   }
 
-  // ---- 2. T_r and the phases
-  if (tid == 0) {
-    if (n >= 2) S.ecx[n - 2] = A[(n - 1) * kEigLd + n - 2];  // last subdiagonal, no reflector
-    cd ph = {1.0, 0.0};
-    S.ph[0] = ph;
-    for (int i = 0; i < n; ++i) {
-      S.d[i] = A[i * kEigLd + i].x;
-      if (i + 1 < n) {
-        const cd ei = S.ecx[i];
-        const double mag = sqrt(ei.x * ei.x + ei.y * ei.y);
-        S.e[i] = mag;
-        if (mag > 0.0) ph = {(ph.x * ei.x - ph.y * ei.y) / mag, (ph.x * ei.y + ph.y * ei.x) / mag};
-        S.ph[i + 1] = ph;
-      }
+  // ---- 2. T_r, the phases and the Gershgorin bounds, one lane per row
+  //         (wave 0): the phases d_0 = 1, d_{i+1} = d_i e_i / |e_i| are a
+  //         prefix product of unit numbers over the lanes
+  if (wave == 0) {
+    const int i = lane;
+    double di = 0.0, mag = 0.0;
+    cd u = {1.0, 0.0};
+    if (i < n) di = A[i * kEigLd + i].x;
+    if (i + 1 < n) {
+      const cd ei = i == n - 2 ? A[(n - 1) * kEigLd + n - 2] : S.ecx[i];  // the last one has no reflector
+      if (i == n - 2) S.ecx[i] = ei;
+      mag = sqrt(ei.x * ei.x + ei.y * ei.y);
+      if (mag > 0.0) u = {ei.x / mag, ei.y / mag};
     }
-    double lo = 1e300, hi = -1e300, nrm = 0.0, emax2 = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double r = (i > 0 ? S.e[i - 1] : 0.0) + (i + 1 < n ? S.e[i] : 0.0);
-      lo = fmin(lo, S.d[i] - r);
-      hi = fmax(hi, S.d[i] + r);
-      nrm = fmax(nrm, fabs(S.d[i]) + r);
-      if (i + 1 < n) emax2 = fmax(emax2, S.e[i] * S.e[i]);
+    cd p = u;  // inclusive product u_0 ... u_i
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const cd q = {__shfl_up(p.x, o, 64), __shfl_up(p.y, o, 64)};
+      if (lane >= o) p = {q.x * p.x - q.y * p.y, q.x * p.y + q.y * p.x};
     }
-    S.scal[0] = lo - 1e-14 * nrm - 1e-300;
-    S.scal[1] = hi + 1e-14 * nrm + 1e-300;
-    S.scal[2] = nrm;
-    S.scal[3] = 2.3e-308 * fmax(1.0, emax2);  // smallest pivot allowed in the Sturm recurrence
+    if (i < n) S.d[i] = di;
+    if (i + 1 < n) {
+      S.e[i] = mag;
+      S.ph[i + 1] = p;
+    }
+    if (i == 0) S.ph[0] = {1.0, 0.0};
+    const double eprev = __shfl_up(mag, 1, 64);
+    const double r = (i > 0 ? eprev : 0.0) + mag;  // mag = 0 on the last row and beyond
+    double lo = i < n ? di - r : 1e300, hi = i < n ? di + r : -1e300;
+    double nrm = i < n ? fabs(di) + r : 0.0, emax2 = mag * mag;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      lo = fmin(lo, __shfl_xor(lo, o, 64));
+      hi = fmax(hi, __shfl_xor(hi, o, 64));
+      nrm = fmax(nrm, __shfl_xor(nrm, o, 64));
+      emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
+    }
+    if (i == 0) {
+      S.scal[0] = lo - 1e-14 * nrm - 1e-300;
+      S.scal[1] = hi + 1e-14 * nrm + 1e-300;
+      S.scal[2] = nrm;
+      S.scal[3] = 2.3e-308 * fmax(1.0, emax2);  // smallest pivot allowed in the Sturm recurrence
+    }
   }
   __syncthreads();
 
@@ -288,11 +307,11 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
     const int t = lane;
     if (t < nev) {
       const double lm = S.lam[t];
-      // inverse iteration on T_r - lm, rows kept in U[(3 t + c) * kEigMax + i]
-      double* y = S.Y + t * kEigMax;
-      double* u0 = S.U + (3 * t + 0) * kEigMax;
-      double* u1 = S.U + (3 * t + 1) * kEigMax;
-      double* u2 = S.U + (3 * t + 2) * kEigMax;
+      // inverse iteration on T_r - lm, rows kept in U[(3 t + c) * kEigYs + i]
+      double* y = S.Y + t * kEigYs;
+      double* u0 = S.U + (3 * t + 0) * kEigYs;
+      double* u1 = S.U + (3 * t + 1) * kEigYs;
+      double* u2 = S.U + (3 * t + 2) * kEigYs;
       const double tiny = 2.2e-16 * fmax(nrm, 1e-300);
       unsigned h = 0x9E3779B9u * (unsigned)(t + 1);
       for (int i = 0; i < n; ++i) {  // fixed pseudo-random start in [-1, 1)
@@ -359,11 +378,11 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
   // component i of every vector, so only the wave sums cross lanes
   if (wave == 0) {
     for (int t2 = 0; t2 < nev; ++t2) {
-      double* yt = S.Y + t2 * kEigMax;
+      double* yt = S.Y + t2 * kEigYs;
       double v = lane < n ? yt[lane] : 0.0;
       for (int pass = 0; pass < 2; ++pass) {
         for (int s2 = S.cstart[t2]; s2 < t2; ++s2) {
-          const double ys = lane < n ? S.Y[s2 * kEigMax + lane] : 0.0;
+          const double ys = lane < n ? S.Y[s2 * kEigYs + lane] : 0.0;
           v -= wave_sum64(ys * v) * ys;
         }
         const double nn = wave_sum64(v * v);
@@ -383,7 +402,7 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
 #pragma unroll
     for (int s2 = 0; s2 < kPerWave; ++s2) {
       const int t = wave + kEigWaves * s2;
-      const double yv = (t < nev && lane < n) ? S.Y[t * kEigMax + lane] : 0.0;
+      const double yv = (t < nev && lane < n) ? S.Y[t * kEigYs + lane] : 0.0;
       zi[s2] = lane < n ? cd{S.ph[lane].x * yv, S.ph[lane].y * yv} : cd{0.0, 0.0};
     }
     for (int j = n - 3; j >= 0; --j) {
