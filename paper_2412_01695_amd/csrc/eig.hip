@@ -11,7 +11,7 @@
 //      w = p - (g/2)(u^H p) u; the u_j stay below the diagonal;
 //   2. a diagonal phase change D (d_0 = 1, d_{j+1} = d_j e_j / |e_j|) making
 //      T = D T_r D^H with T_r real symmetric, off-diagonal |e_j|;
-//   3. eigenvalues of T_r by multisection on Sturm counts (16 points per step,
+//   3. eigenvalues of T_r by multisection on Sturm counts (8 points per step,
 //      eight lanes per eigenvalue);
 //   4. eigenvectors of T_r by inverse iteration, Gaussian elimination with
 //      partial pivoting on T_r - lambda (one lane each, from a fixed
@@ -257,37 +257,33 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
   }
   __syncthreads();
 
-  // ---- 3. eigenvalues of T_r: eight work-items per eigenvalue, two points
-  //         each; every step counts the eigenvalues below 16 interior points of
-  //         the bracket (Sturm sequences, the two of a work-item interleaved)
-  //         and keeps the seventeenth of it that holds eigenvalue t
+  // ---- 3. eigenvalues of T_r: eight work-items per eigenvalue, one point
+  //         each; every step counts the eigenvalues below 8 interior points of
+  //         the bracket (Sturm sequences) and keeps the ninth of it that holds
+  //         eigenvalue t.  The stage is bound by the instructions one wave
+  //         issues, so one sequence per work-item (more steps, each half as
+  //         long) beats two, and more work-items per eigenvalue would put two
+  //         waves on a SIMD.
   {
     const int t = tid >> 3, sub = tid & 7;
     if (t < nev) {  // whole groups of eight
       const double pivmin = S.scal[3];
       double lo = S.scal[0], hi = S.scal[1];
-      for (int it = 0; it < 100; ++it) {
+      for (int it = 0; it < 200; ++it) {
         if (!(hi - lo > 4.5e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
-        const double xa = lo + (hi - lo) * ((2 * sub + 1) / 17.0);
-        const double xb = lo + (hi - lo) * ((2 * sub + 2) / 17.0);
-        int ca = 0, cb = 0;
-        double qa = S.d[0] - xa, qb = S.d[0] - xb;
+        const double xa = lo + (hi - lo) * ((sub + 1) / 9.0);
+        int ca = 0;
+        double qa = S.d[0] - xa;
         if (fabs(qa) < pivmin) qa = -pivmin;
-        if (fabs(qb) < pivmin) qb = -pivmin;
         ca += qa < 0.0;
-        cb += qb < 0.0;
         for (int i = 1; i < n; ++i) {
           const double di = S.d[i], e2 = S.e[i - 1] * S.e[i - 1];
           qa = (di - xa) - e2 * rcp_nr(qa);
-          qb = (di - xb) - e2 * rcp_nr(qb);
           if (fabs(qa) < pivmin) qa = -pivmin;
-          if (fabs(qb) < pivmin) qb = -pivmin;
           ca += qa < 0.0;
-          cb += qb < 0.0;
         }
         double lc = lo, hc = hi;
-        if (ca <= t) lc = xa; else hc = fmin(hc, xa);
-        if (cb <= t) lc = fmax(lc, xb); else hc = fmin(hc, xb);
+        if (ca <= t) lc = xa; else hc = xa;
         for (int o = 1; o < 8; o <<= 1) {
           lc = fmax(lc, __shfl_xor(lc, o, 64));
           hc = fmin(hc, __shfl_xor(hc, o, 64));
