@@ -1,22 +1,26 @@
 """Benchmark: batched H|psi> over many k-points on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config 2] [--no-cpu]
-                    [--no-solve] [--serve-requests 200]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config 4] [--no-cpu]
+                    [--no-solve] [--serve-requests 1000]
 
 A step is one pw_h_psi over the whole batch of the workload (every k-point
 and band in one launch, inputs resident in HBM).  The default workload is
-the 512-k-point fcc cell (ecut 30 Ry, FFT 24^3, 20 bands, 8 projectors);
-value is its FP64 throughput in k-band H|psi> per second, and the same
-batch is timed in mixed precision (complex64, FP32 accumulation) beside it.
-The dominant kernel's roofline fraction is computed from the algorithmic
-flop count of the pruned FFT pipeline (see `algorithmic_work`) over its
-average launch time measured with HIP events on the launch stream.  The
-CPU baseline is the FP64 oracle (dense H_k psi) timed on this host.
-Beside the step throughput it reports the Davidson time-to-solution of the
-same batch (FP64 to 1e-10 Ry and mixed precision refined to 1e-6 Ry, with
-the eigenvalue error against the oracle's dense diagonalisation on sampled
-k-points) and the p50/p99 latency of the continuous-batching server on a
-Poisson stream of Davidson requests.  Prints one JSON line.
+the 1728-k-point fcc cell (ecut 40 Ry, FFT 36^3, 24 bands, 4 projectors),
+the configuration of the FP64-vs-mixed metric; value is its FP64 throughput
+in k-band H|psi> per second, and the same batch is timed in mixed precision
+(complex64, FP32 accumulation) beside it.  The dominant kernel's roofline
+fraction is computed from the algorithmic flop count of the pruned FFT
+pipeline (see `algorithmic_work`) over its average launch time measured with
+HIP events on the launch stream.  The CPU baseline is the FP64 oracle's
+dense route (H_k psi_k by zgemm per k, H_k built outside the timed region),
+on a process pool over the host cores.  Beside the step throughput it
+reports the H|psi> throughput of the 512- and 2048-k workloads, the Davidson
+time-to-solution of the headline batch (FP64 to 1e-10 Ry; mixed precision to
+1e-6 Ry, with and without its FP64 refinement, and the eigenvalue error of
+each against the oracle's dense diagonalisation on sampled k-points), the
+DFPT CG at q = 0 and at the paper's q, and the p50/p99 latency of the
+continuous-batching server on a Poisson stream of Davidson requests.  Prints
+one JSON line.
 """
 from __future__ import annotations
 
@@ -49,6 +53,11 @@ MEASURED_TRAFFIC = {
         "fetch_scale": 2.0, "write_scale": 1.0,
         "profile": "profiles/hpsi_fp64_fcc1-ecut30-fft24-512k.md"},
 }
+
+
+def progress(msg):
+    """One line on stderr per finished stage (the JSON result goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -105,33 +114,82 @@ def algorithmic_work(cfg, miller_by_k, nbnd, cbytes=16, with_3pass=False):
     return flops / k, io / k
 
 
-def cpu_baseline(cfg, vloc, miller_by_k, min_seconds=10.0, max_rounds=3):
-    """The FP64 oracle (build H_k densely, multiply) over the whole batch,
-    repeated until about min_seconds of CPU work; k-band/s."""
-    from oracle import basis, hamiltonian as ham
+def _cpu_worker(cfg, ks, runs, reps, barrier, out_q):
+    """One process of the CPU baseline: H_k of its k-points built (timed apart),
+    then `runs` passes of H_k psi_k (zgemm) over them `reps` times, each pass
+    started at the barrier shared by all processes."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hamiltonian as ham
     from paper_2412_01695_amd import synth
 
     def bfn(c, ik, m):
         return synth.beta_values(c, synth.q_vectors(c, ik, m))
 
-    psis = []
-    for ik in range(cfg.nk):
-        m, _ = basis.sphere(cfg.lat, cfg.kpts[ik], cfg.ecut_ry)
-        psis.append(synth.psi_guess(cfg, ik, m))
-    rounds, t0 = 0, time.perf_counter()
-    while True:
-        ham.h_psi(cfg, vloc, bfn, psis)
-        rounds += 1
-        el = time.perf_counter() - t0
-        if el >= min_seconds or rounds >= max_rounds:
-            break
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        vt = ham.vtilde(synth.vloc_grid(cfg))
+        hs, ps = [], []
+        for ik in ks:
+            kp = ham.KPoint(cfg, int(ik), vt, bfn)
+            hs.append(kp.h)
+            ps.append(np.ascontiguousarray(synth.psi_guess(cfg, int(ik), kp.miller).T))
+        build = time.perf_counter() - t0
+        times = []
+        for _ in range(runs):
+            barrier.wait()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                for h, p in zip(hs, ps):
+                    h @ p
+            times.append(time.perf_counter() - t0)
+    out_q.put((build, times))
+
+
+def cpu_baseline(cfg_ids=(4, 2, 3), k_per_core=(27, 32, 32), runs=5, reps=8):
+    """The oracle's FP64 dense route, as the CPU reference of the metric: per
+    k-point, H_k (npw x npw, built from the oracle's naive-DFT V~ and the
+    projectors) times psi_k (npw x nbnd) in one zgemm.  One process per host
+    core (BLAS single-threaded in each), a bounded sample of k-points of each
+    workload split across them; H_k construction is timed separately and
+    excluded; each of `runs` passes starts at a barrier and takes as long as
+    its slowest process; the median pass gives k-band/s."""
+    import multiprocessing as mp
+
+    from paper_2412_01695_amd import synth
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    return {"value": rounds * cfg.nk * cfg.nbnd / el, "unit": "k-band/s", "cores": cores, "kind": "oracle",
-            "sample": f"whole batch ({cfg.nk} k x {cfg.nbnd} bands) x {rounds} round(s), {el:.1f} s, "
-                      f"numpy/OpenBLAS threads over {cores} cores"}
+    ctx = mp.get_context("fork")
+    res = {}
+    for cid, kpc in zip(cfg_ids, k_per_core):
+        cfg = synth.make_config(cid)
+        nks = min(cfg.nk, kpc * cores)
+        ks = np.unique(np.linspace(0, cfg.nk - 1, nks).astype(int))
+        chunks = [ks[i::cores] for i in range(cores)]
+        chunks = [c for c in chunks if len(c)]
+        barrier = ctx.Barrier(len(chunks))
+        q = ctx.Queue()
+        procs = [ctx.Process(target=_cpu_worker, args=(cfg, c, runs, reps, barrier, q)) for c in chunks]
+        t0 = time.perf_counter()
+        for p in procs:
+            p.start()
+        got = [q.get() for _ in procs]
+        for p in procs:
+            p.join()
+        wall = time.perf_counter() - t0
+        per_run = np.max(np.array([g[1] for g in got]), axis=0)   # slowest process of each pass
+        med = float(np.median(per_run))
+        res[cfg.name] = {"value": reps * len(ks) * cfg.nbnd / med, "unit": "k-band/s", "cores": len(chunks),
+                         "kind": "oracle",
+                         "sample": f"{len(ks)} of {cfg.nk} k-points x {cfg.nbnd} bands, {reps} times per pass "
+                                   f"(H_k psi_k zgemm, dense "
+                                   f"H_k built outside the timed passes in {max(g[0] for g in got):.1f} s), "
+                                   f"{len(chunks)} processes x 1 BLAS thread, median of {runs} passes "
+                                   f"({med * 1e3:.1f} ms each), {wall:.1f} s wall",
+                         "passes_ms": [float(x) * 1e3 for x in per_run]}
+    return res
 
 
 def oracle_eig_error(cfg, vloc, miller_lib, eigs, nsample=8):
@@ -174,8 +232,11 @@ def time_davidson(torch, mkpw, sysm, prec, tol_ry):
         st, eig, iters, conv = mkpw.pw_davidson(sysm.ctx, prec, cfg.nbnd, psi, cfg.nk, tol_ry, 300)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+    opt = lambda k: mkpw.pw_get_option(sysm.ctx, k)
     return {"seconds": times[1], "first_seconds": times[0], "status": int(st), "converged_k": int(conv.sum()),
-            "iters_min": int(iters.min()), "iters_max": int(iters.max()), "tol_ry": tol_ry}, eig
+            "iters_min": int(iters.min()), "iters_max": int(iters.max()), "tol_ry": tol_ry,
+            "hpsi_kband_applications": opt("last_hpsi_kbands"), "iterations": opt("last_iterations"),
+            "graph_replays": opt("last_graph_replays")}, eig
 
 
 def dfpt_sample(torch, mkpw, cfg_id, thr=1e-24):
@@ -230,7 +291,9 @@ def dfpt_sample(torch, mkpw, cfg_id, thr=1e-24):
             ax = hx - eps_t * x + a_t * torch.bmm(ux.transpose(1, 2).contiguous(), u)
             rel = (torch.linalg.vector_norm(ax - rhs, dim=2) / torch.linalg.vector_norm(rhs, dim=2)).max().item()
             out[name] = {"seconds": dt, "first_seconds": times[0], "status": int(st), "iters_min": int(it.min()),
-                         "iters_max": int(it.max()), "systems_per_s": cfg.nk * nocc / dt, "max_rel_residual": rel}
+                         "iters_max": int(it.max()), "systems_per_s": cfg.nk * nocc / dt, "max_rel_residual": rel,
+                         "hpsi_kband_applications": mkpw.pw_get_option(sysm.ctx, "last_hpsi_kbands"),
+                         "graph_replays": mkpw.pw_get_option(sysm.ctx, "last_graph_replays")}
         return out
     finally:
         dsys.close()
@@ -293,21 +356,19 @@ def overlap_sample(torch, mkpw, cfg_id, steps, warmup, solve, check):
 
 
 def dfpt_q_sample(torch, mkpw, cfg_id):
-    """DFPT at the paper's wavevector q on a whole workload: FP64 Davidson at the k and
-    k+q lists, the right-hand sides -(1 - P_v) dV u on the device for nocc occupied
-    bands, the CG at k+q for every (k, occupied band) and the induced density of
-    Eq. drho.  The CG needs every system positive definite on the conduction states
-    (eps_{k+q, nocc+1} > eps_{k, nocc} at every k); these model bands overlap across
-    k and k+q (a metal, which the paper treats with smearing), so when no occupied
-    count has such a gap the CG is not run and the density is formed from the
-    right-hand sides in place of the solutions (its cost does not depend on the
-    values)."""
+    """DFPT at the paper's wavevector q on a whole workload made insulating: the
+    two-atom cell with its local potential deepened until the lowest nocc bands
+    are separated from the rest at every k and k+q (synth.gapped).  FP64
+    Davidson at the k and k+q lists, the right-hand sides -(1 - P_v^{k+q}) dV u_k
+    on the device, the CG at k+q for every (k, occupied band) in FP64 and mixed
+    precision (true relative residual checked with one more H application on
+    the k+q context), and the induced density of Eq. drho from the solutions."""
     from paper_2412_01695_amd import synth
     from paper_2412_01695_amd.system import System
 
-    cfg = synth.make_config(cfg_id)
+    cfg = synth.gapped(synth.make_config(cfg_id))
     q = synth.q_paper()
-    nocc = int(cfg.extra.get("nocc", cfg.nbnd))
+    nocc = int(cfg.extra["nocc"])
     sk = System(cfg, 0)
     sq = System(synth.shifted(cfg, q), 0, stream=sk.stream)
     torch.cuda.set_stream(sk.stream)
@@ -328,9 +389,10 @@ def dfpt_q_sample(torch, mkpw, cfg_id):
                 times.append(time.perf_counter() - t0)
             out[f"davidson_{name}_s"] = times[1]
             out[f"davidson_{name}_first_s"] = times[0]
+            out[f"davidson_{name}_converged_k"] = int(conv.sum())
             eig[name], vec[name] = e, u
         ek, eq = eig["k"], eig["k+q"]
-        gap = float(np.min(eq[:, nocc] - ek[:, nocc - 1]))
+        gap = float(np.min(eq[:, nocc]) - np.max(ek[:, nocc - 1]))
         uk = vec["k"][:, :nocc].contiguous()
         uq = vec["k+q"][:, :nocc].contiguous()
         dv = synth.dv_complex_grid(cfg)
@@ -343,33 +405,41 @@ def dfpt_q_sample(torch, mkpw, cfg_id):
         npk, npq = sk.npw.astype(np.float64), sq.npw.astype(np.float64)
         pair_flops = float(np.sum(8.0 * npk * npq * nocc))
         out.update({
-            "workload": f"{cfg.name} at q = (2 pi/a)(-1/8, -1/4, 3/8): {cfg.nk} k and {cfg.nk} k+q, "
-                        f"{nocc} occupied bands = rhs per k, FFT {cfg.fft[0]}^3, complex periodic dV",
-            "systems": cfg.nk * nocc, "min_gap_kq_minus_k_ha": gap,
+            "workload": f"{cfg.name} at q = (2 pi/a)(-1/8, -1/4, 3/8): {cfg.nk} k and {cfg.nk} k+q, local "
+                        f"potential x{cfg.extra['vloc_scale']:g} (insulating), {nocc} occupied bands = rhs per k, "
+                        f"FFT {cfg.fft[0]}^3, complex periodic dV",
+            "systems": cfg.nk * nocc, "gap_kq_min_minus_k_max_ha": gap,
             "rhs_s": t_rhs, "rhs_tflops": pair_flops / t_rhs / 1e12, "pair_flops": pair_flops})
-        du = rhs
-        if gap > 0.01:
-            eps = np.ascontiguousarray(ek[:, :nocc])
-            hi = np.maximum(ek[:, nocc - 1], eq[:, nocc - 1])
-            lo = np.minimum(ek[:, 0], eq[:, 0])
-            alpha = np.maximum(2.0 * (hi - lo), 0.1)
-            x = torch.zeros_like(rhs)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, it = mkpw.pw_dfpt_cg(sq.ctx, mkpw.PW_FP64, nocc, uq, eps, alpha, nocc, rhs, x, 1e-24, 2000)
-            torch.cuda.synchronize()
-            out["cg_fp64"] = {"seconds": time.perf_counter() - t0, "status": int(st), "iters_min": int(it.min()),
-                              "iters_max": int(it.max())}
-            du = x
-        else:
-            out["cg_fp64"] = None
-            out["note"] = ("no gap between the occupied k and the empty k+q bands at every k (metallic model "
-                           "bands): CG not run, drho timed on the right-hand sides")
+        eps = np.ascontiguousarray(ek[:, :nocc])
+        hi = np.maximum(ek[:, nocc - 1], eq[:, nocc - 1])
+        lo = np.minimum(ek[:, 0], eq[:, 0])
+        alpha = np.maximum(2.0 * (hi - lo), 0.1)
+        eps_t = torch.from_numpy(eps).cuda()[:, :, None]
+        a_t = torch.from_numpy(alpha).cuda()[:, None, None]
+        x = None
+        for name, prec in (("cg_fp64", mkpw.PW_FP64), ("cg_mixed", mkpw.PW_MIXED)):
+            times = []
+            for _ in range(2):
+                x = torch.zeros_like(rhs)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, it = mkpw.pw_dfpt_cg(sq.ctx, prec, nocc, uq, eps, alpha, nocc, rhs, x, 1e-24, 2000)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            hx = torch.empty_like(x)
+            mkpw.pw_h_psi(sq.ctx, mkpw.PW_FP64, nocc, x, hx)
+            ux = torch.bmm(uq.conj(), x.transpose(1, 2).contiguous())
+            ax = hx - eps_t * x + a_t * torch.bmm(ux.transpose(1, 2).contiguous(), uq)
+            rel = (torch.linalg.vector_norm(ax - rhs, dim=2) / torch.linalg.vector_norm(rhs, dim=2)).max().item()
+            out[name] = {"seconds": times[1], "first_seconds": times[0], "status": int(st),
+                         "iters_min": int(it.min()), "iters_max": int(it.max()),
+                         "systems_per_s": cfg.nk * nocc / times[1], "max_rel_residual": rel,
+                         "hpsi_kband_applications": mkpw.pw_get_option(sq.ctx, "last_hpsi_kbands")}
         w = np.full(cfg.nk, 1.0 / cfg.nk)
         drho = torch.empty(cfg.fft, dtype=torch.complex128, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        mkpw.pw_drho(sq.ctx, sk.ctx, nocc, w, uk, du, drho)
+        mkpw.pw_drho(sq.ctx, sk.ctx, nocc, w, uk, x, drho)
         torch.cuda.synchronize()
         t_rho = time.perf_counter() - t0
         out.update({"drho_s": t_rho, "drho_tflops": pair_flops / t_rho / 1e12})
@@ -385,13 +455,43 @@ def serving_sample(n, rate=20.0):
     serve.prewarm(reqs)
     srv = serve.Server(0, 8)
     t = time.monotonic()
-    serve.replay(reqs, srv)
+    serve.replay(reqs, srv, report=lambda n: progress(f"serving: {n} requests submitted"))
     wall = time.monotonic() - t
     srv.close()
     out = serve.summarize(reqs, wall)
     out["stream"] = (f"{n} Poisson arrivals at {rate:g}/s: nk U{{16..1024}}, ecut U[20,45] Ry, nbnd U{{8..32}}, "
                      f"1-2 atoms; mixed precision refined to 1e-6 Ry; 8 slots, 64 GiB HBM budget")
     return out
+
+
+def hpsi_sample(torch, mkpw, cid, steps, warmup):
+    """FP64 and mixed H|psi> throughput of another whole workload, with the
+    roofline fractions of its autotuned kernels."""
+    from paper_2412_01695_amd import synth
+    from paper_2412_01695_amd.system import System
+
+    cfg = synth.make_config(cid)
+    s = System(cfg, 0)
+    torch.cuda.set_stream(s.stream)
+    try:
+        psi64 = torch.from_numpy(s.psi_guess()).cuda()
+        h64 = torch.empty_like(psi64)
+        psi32 = psi64.to(torch.complex64)
+        h32 = torch.empty_like(psi32)
+        nkb = cfg.nk * cfg.nbnd
+        flops_kb, io_kb = algorithmic_work(cfg, s.miller, cfg.nbnd, 16)
+        out = {"config": f"{cfg.nk} k-points (npw {int(s.npw.min())}-{int(s.npw.max())}), {cfg.nbnd} bands, "
+                         f"FFT {cfg.fft[0]}^3, {cfg.nproj} projectors", "flops_per_kband": flops_kb}
+        for name, prec, psi, h, peak in (("fp64", mkpw.PW_FP64, psi64, h64, PEAK_FP64_TFLOPS),
+                                         ("mixed", mkpw.PW_MIXED, psi32, h32, PEAK_FP32_TFLOPS)):
+            ms, _ = time_hpsi(torch, mkpw, s.ctx, prec, cfg.nbnd, psi, h, steps, warmup)
+            tf = flops_kb * nkb / (ms * 1e-3) / 1e12
+            out[name] = {"ms_per_call": ms, "kband_per_s": nkb / (ms * 1e-3), "tflops": tf, "roofline_frac": tf / peak,
+                         "shape": {k: mkpw.pw_get_option(s.ctx, f"hpsi_{k}_tuned")
+                                   for k in ("variant", "slab", "threads")}}
+        return cfg.name, out
+    finally:
+        s.close()
 
 
 def time_hpsi(torch, mkpw, ctx, prec, nbnd, psi, hpsi, steps, warmup):
@@ -415,10 +515,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--other-configs", default="2,3",
+                    help="workloads whose H|psi> throughput is reported beside the headline ('' to skip)")
     ap.add_argument("--dfpt-config", type=int, default=3, help="workload of the DFPT CG sample (0: skip)")
     ap.add_argument("--overlap-config", type=int, default=2,
                     help="workload of the overlap (S psi, generalized Davidson) sample (0: skip)")
@@ -470,9 +572,11 @@ def main():
     if args.only in ("fp64", "both"):
         ms64, wall64 = time_hpsi(torch, mkpw, sysm.ctx, mkpw.PW_FP64, nbnd, psi64, h64, args.steps, args.warmup)
         out["fp64"], shapes["fp64"] = ms64, shape()
+        progress(f"H|psi> fp64 {cfg.name}: {ms64:.4f} ms")
     if args.only in ("mixed", "both"):
         ms32, wall32 = time_hpsi(torch, mkpw, sysm.ctx, mkpw.PW_MIXED, nbnd, psi32, h32, args.steps, args.warmup)
         out["mixed"], shapes["mixed"] = ms32, shape()
+        progress(f"H|psi> mixed {cfg.name}: {ms32:.4f} ms")
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -529,26 +633,47 @@ def main():
     eigs = {}
     if not args.no_solve:
         solve = {}
-        for name, prec, tol in (("fp64", mkpw.PW_FP64, 1e-10), ("mixed", mkpw.PW_MIXED, 1e-6)):
+        for name, prec, tol, refine in (("fp64", mkpw.PW_FP64, 1e-10, 1), ("mixed", mkpw.PW_MIXED, 1e-6, 1),
+                                        ("mixed_before_refinement", mkpw.PW_MIXED, 1e-6, 0)):
+            mkpw.pw_set_option(sysm.ctx, "mixed_refine", refine)
             solve[name], eigs[name] = time_davidson(torch, mkpw, sysm, prec, tol)
             solve[name]["kband_per_s"] = nkb / solve[name]["seconds"]
+            progress(f"Davidson {name}: {solve[name]['seconds']:.4f} s")
+        mkpw.pw_set_option(sysm.ctx, "mixed_refine", 1)
         res["solve"] = solve
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(cfg, sysm.vloc, sysm.miller)
         if eigs:
             err, ks = oracle_eig_error(cfg, sysm.vloc, sysm.miller, eigs)
             for name in eigs:
                 res["solve"][name]["max_eig_err_vs_oracle_ry"] = err[name]
             res["solve"]["oracle_k_sample"] = ks
+            progress(f"oracle eigenvalue errors (Ry): {err}")
     sysm.close()
+    if args.other_configs:
+        res["hpsi_workloads"] = {}
+        for cid in (int(x) for x in args.other_configs.split(",")):
+            if cid != args.config:
+                name, entry = hpsi_sample(torch, mkpw, cid, args.steps, args.warmup)
+                res["hpsi_workloads"][name] = entry
+                progress(f"H|psi> {name}: fp64 {entry['fp64']['ms_per_call']:.4f} ms, "
+                         f"mixed {entry['mixed']['ms_per_call']:.4f} ms")
+    if not args.no_cpu:
+        allcpu = cpu_baseline()
+        progress("cpu baseline: " + ", ".join(f"{k} {v['value']:.0f} k-band/s" for k, v in allcpu.items()))
+        res["cpu_baseline"] = dict(allcpu.get(cfg.name) or next(iter(allcpu.values())))
+        res["cpu_baseline_workloads"] = allcpu
     if args.overlap_config > 0:
         res["overlap"] = overlap_sample(torch, mkpw, args.overlap_config, args.steps, args.warmup,
                                         not args.no_solve, not args.no_cpu)
+        progress("overlap sample done")
     if args.dfpt_config > 0:
         res["dfpt"] = dfpt_sample(torch, mkpw, args.dfpt_config)
+        progress("DFPT q = 0 done")
         res["dfpt_q"] = dfpt_q_sample(torch, mkpw, args.dfpt_config)
+        progress("DFPT q != 0 done")
     if args.serve_requests > 0:
         res["serving"] = serving_sample(args.serve_requests)
+        progress(f"serving: p50 {res['serving']['p50_s']:.3f} s, p99 {res['serving']['p99_s']:.3f} s")
     print(json.dumps(res))
 
 

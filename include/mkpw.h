@@ -81,13 +81,23 @@ const char* pw_last_error(const pw_ctx* ctx);
  * that leaves; PW_EINVAL otherwise).  Any nonzero shape option fixes the
  * shape: the others default to variant 1, 256 work-items and the widest slab
  * that fits.
- * "tune_log" (nonzero: print each autotuning candidate's time to stderr). */
+ * "tune_log" (nonzero: print each autotuning candidate's time to stderr),
+ * "solver_graph" (default 1: pw_davidson and pw_dfpt_cg capture one iteration
+ * as a HIP graph and replay it; 0: launch every kernel of every iteration
+ * one by one; the results are the same), "mixed_refine" (default 1: the
+ * PW_MIXED Davidson refines in FP64 after its complex64 phase; 0: it returns
+ * the complex64-phase result, for measuring what the refinement adds). */
 pw_status pw_set_option(pw_ctx* ctx, const char* key, int64_t value);
 
 /* Read an option (the keys above), or "hpsi_variant_tuned" / "hpsi_slab_tuned" /
  * "hpsi_threads_tuned" (the shape of this context's last H|psi> launch, 0 if
- * none), "device_bytes" (device memory the context holds now) or "overlap"
- * (1 while overlap coefficients q are set, else 0). */
+ * none), "device_bytes" (device memory the context holds now), "overlap"
+ * (1 while overlap coefficients q are set, else 0), or the context's sizes:
+ * "nk" and "npwx" (0 before pw_set_kpoints), "nproj" (0 without projectors),
+ * "fft1", "fft2", "fft3" (the mesh; 0 before pw_set_cutoff), and what the
+ * last pw_davidson or pw_dfpt_cg did: "last_iterations" (iterations run),
+ * "last_hpsi_kbands" (H applications, one per (k, vector) row each time H is
+ * applied to it), "last_graph_replays" (iterations run as graph replays). */
 pw_status pw_get_option(const pw_ctx* ctx, const char* key, int64_t* value);
 
 /* Direct lattice, rows a1, a2, a3 in bohr (host, 9 doubles).  Resets the
@@ -168,10 +178,15 @@ pw_status pw_s_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* s
  * out (S-orthonormal).  eig_ha: host (nk, nbnd) doubles, eigenvalues in Ha.
  * A k-point is converged when every band's eigenvalue changed by less than
  * tol_ry/2 Ha in the last iteration and its residual norm |H psi - e S psi| is
- * below max(1e-5, sqrt(tol_ry)) (so the eigenvalue error is of order
- * residual^2 / gap).  iters, converged: host (nk) ints, may be NULL.
- * PW_MIXED applies H in complex64 until convergence, then refines in FP64
- * until the eigenvalues change by less than tol_ry/2 Ha.
+ * below 1e-5 (so the eigenvalue error is of order residual^2 / gap).
+ * iters, converged: host (nk) ints, may be NULL.
+ * PW_MIXED applies H in complex64 until every band's eigenvalue changes by
+ * less than max(tol_ry/2, 2e-6) Ha with residual norm below 2e-4 (what an
+ * FP32 H application resolves), then refines with H in FP64 to the FP64
+ * criterion above (option "mixed_refine" = 0 stops after the complex64 phase).
+ * Every per-iteration decision (which bands get a correction, restarts,
+ * dropped blocks) is taken on the device; the host only learns, one iteration
+ * late, whether any k is still active.
  * Returns PW_ENOCONV if some k did not converge within max_iter. */
 pw_status pw_davidson(pw_ctx* ctx, pw_prec prec, int nbnd, void* psi, double* eig_ha, double tol_ry,
                 int max_iter, int32_t* iters, int32_t* converged);
@@ -188,9 +203,12 @@ pw_status pw_davidson(pw_ctx* ctx, pw_prec prec, int nbnd, void* psi, double* ei
  * Preconditioner M_GG = max(1, (|k+G|^2/2) / <psi_nu|T|psi_nu>) with psi_nu
  * = psi_occ row nu (nrhs <= nocc) (Sec. 2.4).  Each system stops when
  * |rho| = |Re <M^-1 r|r>| < thr; converged systems are frozen.
- * iters: host (nk*nrhs) ints, may be NULL.  PW_MIXED applies H in complex64
- * while the residual update and all scalars stay FP64.
- * Returns PW_ENOCONV if some system did not converge within max_iter. */
+ * iters: host (nk*nrhs) ints (updates applied to each system), may be NULL.
+ * PW_MIXED applies H in complex64 while the residual update and all scalars
+ * stay FP64, until every system's |rho| has dropped by 1e-10 from its start,
+ * then recomputes the residual with H in FP64 and continues to thr.
+ * Returns PW_ENOCONV if some system did not converge within max_iter updates
+ * (both phases of PW_MIXED together). */
 pw_status pw_dfpt_cg(pw_ctx* ctx, pw_prec prec, int nocc, const void* psi_occ, const double* eps_ha,
                const double* alpha_ha, int nrhs, const void* rhs, void* dpsi, double thr, int max_iter,
                int32_t* iters);

@@ -14,8 +14,10 @@
 //                        t = A d;  lambda = -Re(d^H r) / Re(d^H t);
 //                        x += lambda d;  r += lambda t;  d_old = d;  rho_old = rho
 //   M_GG = max(1, (|k+G|^2/2) / <u_nu|T|u_nu>)   (Sec. 2.4 preconditioner)
-// The paper keeps rho, gamma and lambda on the CPU; here every scalar stays
-// on the device and the host only reads the per-system "active" flags.
+// The paper keeps rho, gamma and lambda on the CPU; here every scalar and
+// flag stays on the device and the host only reads, one iteration late, how
+// many systems are still active.  max_iter bounds the updates of the whole
+// solve (both phases of the mixed mode together).
 // Mixed precision applies H in complex64 (everything else FP64) until each
 // system's residual has dropped by a fixed factor (or below thr), then
 // recomputes r = A x - b with H in FP64 and continues to thr: the FP32 phase
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(256) void init_resid_kernel(const cd* t, const cd* 
 __global__ __launch_bounds__(256) void step1_kernel(const cd* r, cd* d, const cd* dold, const double* kin,
                                                     const double* tk, const int* npw, int npwx, int nrhs, double* rho,
                                                     double* rho_old, double* rho0, int* active, int first, double thr,
-                                                    double rel) {
+                                                    double rel, int* iters) {
   const long sys = blockIdx.x;
   if (!active[sys]) return;
   const int k = (int)(sys / nrhs);
@@ -124,7 +126,29 @@ __global__ __launch_bounds__(256) void step1_kernel(const cd* r, cd* d, const cd
     }
     d[o + g] = v;
   }
-  if (threadIdx.x == 0) rho[sys] = s;
+  if (threadIdx.x == 0) {
+    rho[sys] = s;
+    iters[sys] += 1;  // one more update for this system
+  }
+}
+
+// number of nonzero flags (one workgroup)
+__global__ __launch_bounds__(1024) void count_active_kernel(const int* __restrict__ a, long n, int* out) {
+  __shared__ int red[16];
+  int s = 0;
+  for (long i = threadIdx.x; i < n; i += 1024) s += a[i] != 0;
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    *out = t;
+  }
+}
+
+__global__ void fill_int_kernel(int* p, long n, int v) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) p[e] = v;
 }
 
 // t -= eps d (when sub_eps) ; lambda = -Re(d^H r)/Re(d^H t) ; x += lambda d ;
@@ -169,6 +193,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
   hipStream_t st = c->stream;
   const int nk = c->nk, npwx = c->npwx;
   const long nsys = (long)nk * nrhs;
+  c->last_iterations = c->last_hpsi_kbands = c->last_graph_replays = 0;
   const size_t nv = (size_t)nsys * npwx;
   DevBufs bf(c);
   cd *r, *d, *dold, *t, *W;
@@ -252,74 +277,137 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     return check_launch(c, "init_resid", st);
   };
 
-  // The host reads the active flags one step late: the flags of step it are
-  // copied to page-locked memory behind step1 and looked at once step it + 1
-  // is queued, so the device never waits for the host between steps.  A step
+  // One unit of work is an update and the next check: t = A d on the active
+  // systems, step 2 (x, r), step 1 (the next d, rho, convergence).  The host
+  // reads only the number of systems still active, one unit late: the count
+  // is copied to page-locked memory behind each unit and looked at once the
+  // next unit is queued, so the device never waits for the host.  A unit
   // queued after every system has converged changes nothing (both step
-  // kernels skip inactive systems, and t is scratch).
+  // kernels skip inactive systems, and t is scratch).  From the second unit of
+  // a phase on, the unit runs as a captured graph, replayed.
+  int* iters_d;
+  int* d_nact;
+  MKPW_TRY(bf.get((size_t)nsys, &iters_d));
+  MKPW_TRY(bf.get((size_t)1, &d_nact));
+  hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)std::min<long>(1024, (nsys + 255) / 256)), dim3(256), 0, st,
+                     iters_d, nsys, 0);
+  MKPW_TRY(check_launch(c, "fill", st));
   HostStage hs(c, st);
-  MKPW_TRY(hs.init(0, 2 * sizeof(int) * nsys));
-  int* slot[2] = {hs.back<int>(0), hs.back<int>(sizeof(int) * nsys)};
+  MKPW_TRY(hs.init(0, 256 + sizeof(int) * nsys));
+  int* slot[2] = {hs.back<int>(0), hs.back<int>(sizeof(int))};
+  int* p_iters = hs.back<int>(256);
   hipEvent_t ev[2] = {nullptr, nullptr};
-  struct Events {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct Cleanup {
     hipEvent_t* e;
-    ~Events() {
+    hipGraph_t* g;
+    hipGraphExec_t* x;
+    ~Cleanup() {
       for (int i = 0; i < 2; ++i)
         if (e[i]) (void)hipEventDestroy(e[i]);
+      if (*x) (void)hipGraphExecDestroy(*x);
+      if (*g) (void)hipGraphDestroy(*g);
     }
-  } ev_guard{ev};
+  } cleanup{ev, &graph, &exec};
   for (int i = 0; i < 2; ++i) MKPW_HIP(c, hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+  auto drop_graph = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  };
 
-  std::vector<int> iters(nsys, 0);
-  MKPW_TRY(restart());
-  int first = 1;
-  bool ok = false;
-  int it_total = 0;
-  for (int it = 1;; ++it) {
-    if (it <= max_iter) {
-      // the FP32 phase of the mixed mode stops at a residual reduction its
-      // H application can still resolve; the FP64 phase runs to thr
-      const double rel = fp64_h ? 0.0 : kRelFp32;
-      hipLaunchKernelGGL(step1_kernel, dim3((unsigned)nsys), dim3(256), 0, st, r, d, dold, c->d_kin, tk, c->d_npw,
-                         npwx, nrhs, rho, rho_old, rho0, active, first, thr, rel);
-      MKPW_TRY(check_launch(c, "cg_step1", st));
-      MKPW_HIP(c, hipMemcpyAsync(slot[it & 1], active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
-      MKPW_HIP(c, hipEventRecord(ev[it & 1], st));
-    }
-    if (it > 1) {
-      // the flags after step1 of step it - 1
-      MKPW_HIP(c, hipEventSynchronize(ev[(it - 1) & 1]));
-      const int* act = slot[(it - 1) & 1];
-      long n_act = 0;
-      for (long s = 0; s < nsys; ++s)
-        if (act[s]) {
-          ++n_act;
-          iters[s] = it_total + it - 1;
-        }
-      if (n_act == 0) {
-        if (!fp64_h) {
-          // FP64 refinement: true residual with H in FP64, then continue
-          fp64_h = true;
-          it_total += it - 1;
-          first = 1;
-          MKPW_TRY(restart());
-          it = 0;
-          continue;
-        }
-        ok = true;
-        break;
-      }
-    }
-    if (it > max_iter) break;
-    first = 0;
+  auto step1 = [&](int first) -> pw_status {
+    // the FP32 phase of the mixed mode stops at a residual reduction its
+    // H application can still resolve; the FP64 phase runs to thr
+    const double rel = fp64_h ? 0.0 : kRelFp32;
+    hipLaunchKernelGGL(step1_kernel, dim3((unsigned)nsys), dim3(256), 0, st, r, d, dold, c->d_kin, tk, c->d_npw, npwx,
+                       nrhs, rho, rho_old, rho0, active, first, thr, rel, iters_d);
+    MKPW_TRY(check_launch(c, "cg_step1", st));
+    hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(1024), 0, st, active, nsys, d_nact);
+    return check_launch(c, "count_active", st);
+  };
+  auto unit = [&]() -> pw_status {
     MKPW_TRY(apply_a(d, active));
     hipLaunchKernelGGL(step2_kernel, dim3((unsigned)nsys), dim3(256), 0, st, t, d, dold, x, r, eps, c->d_npw, npwx,
                        nrhs, rho, rho_old, active, gen ? 0 : 1);
     MKPW_TRY(check_launch(c, "cg_step2", st));
+    return step1(0);
+  };
+  bool use_graph = c->solver_graph && !c->trace;
+  auto run_unit = [&](int in_phase) -> pw_status {
+    if (use_graph && in_phase >= 2) {
+      if (!exec) {
+        bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+          pw_status s = unit();
+          hipGraph_t g = nullptr;
+          const bool ended = hipStreamEndCapture(st, &g) == hipSuccess;
+          if (s != PW_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+          }
+          ok = ended && g && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+          graph = g;
+        }
+        if (!ok) {  // run this and every later unit launch by launch
+          (void)hipGetLastError();
+          drop_graph();
+          use_graph = false;
+          return unit();
+        }
+      }
+      MKPW_HIP(c, hipGraphLaunch(exec, st));
+      ++c->last_graph_replays;
+      return PW_OK;
+    }
+    return unit();
+  };
+  auto post = [&](int u) -> pw_status {
+    MKPW_HIP(c, hipMemcpyAsync(slot[u & 1], d_nact, sizeof(int), hipMemcpyDeviceToHost, st));
+    MKPW_HIP(c, hipEventRecord(ev[u & 1], st));
+    return PW_OK;
+  };
+
+  MKPW_TRY(restart());
+  c->last_hpsi_kbands += nsys;
+  MKPW_TRY(step1(1));
+  MKPW_TRY(post(0));
+  bool ok = false;
+  int phase_first = 1;  // first unit of the current phase
+  int u = 1;
+  for (u = 1;; ++u) {
+    if (u <= max_iter) {
+      MKPW_TRY(run_unit(u - phase_first + 1));
+      MKPW_TRY(post(u));
+    }
+    // the check that preceded unit u
+    MKPW_HIP(c, hipEventSynchronize(ev[(u - 1) & 1]));
+    const int n_act = *slot[(u - 1) & 1];
+    if (u <= max_iter) c->last_hpsi_kbands += n_act;
+    if (n_act == 0) {
+      if (!fp64_h) {
+        // FP64 refinement: true residual with H in FP64, then continue
+        fp64_h = true;
+        drop_graph();
+        MKPW_TRY(restart());
+        c->last_hpsi_kbands += nsys;
+        MKPW_TRY(step1(1));
+        MKPW_TRY(post(u));
+        phase_first = u + 1;
+        continue;
+      }
+      ok = true;
+      break;
+    }
+    if (u > max_iter) break;
   }
+  c->last_iterations = std::min(u, max_iter);
+  MKPW_HIP(c, hipMemcpyAsync(p_iters, iters_d, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
   MKPW_HIP(c, hipStreamSynchronize(st));
   if (iters_out)
-    for (long s = 0; s < nsys; ++s) iters_out[s] = iters[s];
+    for (long s = 0; s < nsys; ++s) iters_out[s] = p_iters[s];
   if (!ok) return set_err(c, PW_ENOCONV, "CG: some systems did not converge");
   return PW_OK;
 }

@@ -292,6 +292,10 @@ pw_status pw_set_option(pw_ctx* c, const char* key, int64_t value) {
     c->hpsi_threads = value;
   } else if (k == "tune_log") {
     c->tune_log = value;
+  } else if (k == "solver_graph") {
+    c->solver_graph = value != 0;
+  } else if (k == "mixed_refine") {
+    c->mixed_refine = value != 0;
   } else {
     return set_err(c, PW_EINVAL, "unknown option '" + k + "'");
   }
@@ -311,7 +315,16 @@ pw_status pw_get_option(const pw_ctx* c, const char* key, int64_t* value) {
   else if (k == "hpsi_slab_tuned") *value = c->last_hpsi_slab;
   else if (k == "hpsi_threads_tuned") *value = c->last_hpsi_threads;
   else if (k == "tune_log") *value = c->tune_log;
+  else if (k == "solver_graph") *value = c->solver_graph;
+  else if (k == "mixed_refine") *value = c->mixed_refine;
+  else if (k == "last_iterations") *value = c->last_iterations;
+  else if (k == "last_hpsi_kbands") *value = c->last_hpsi_kbands;
+  else if (k == "last_graph_replays") *value = c->last_graph_replays;
   else if (k == "overlap") *value = c->have_q ? 1 : 0;
+  else if (k == "nk") *value = c->have_k ? c->nk : 0;
+  else if (k == "npwx") *value = c->have_k ? c->npwx : 0;
+  else if (k == "nproj") *value = c->have_proj ? c->nproj : 0;
+  else if (k == "fft1" || k == "fft2" || k == "fft3") *value = c->have_cutoff ? c->fft[k[3] - '1'] : 0;
   else if (k == "device_bytes") {
     int64_t b = 0;
     for (auto& m : c->owned) b += (int64_t)m.bytes;

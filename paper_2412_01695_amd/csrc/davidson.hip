@@ -177,6 +177,117 @@ __global__ void copy_rows_kernel(const cd* src, int src_rows, cd* dst, int dst_r
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) d[e] = s[e];
 }
 
+template <class T>
+__global__ void fill_kernel(T* p, long n, T v) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) p[e] = v;
+}
+
+// ---- per-k bookkeeping, decided on the device so that an iteration needs no
+//      host round trip (and can be replayed as a captured graph)
+
+// Every k restarts its basis from nothing with nbnd new vectors to
+// orthonormalise: nb = 0, nnc = nbnd, active, no previous eigenvalues.
+__global__ void dav_reset_kernel(int nk, int nbnd, int* nb, int* nnc, int* active, int* force_restart,
+                                 double* th_old) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nk) return;
+  nb[k] = 0;
+  nnc[k] = nbnd;
+  active[k] = 1;
+  force_restart[k] = 0;
+  for (int j = 0; j < nbnd; ++j) th_old[(long)k * nbnd + j] = HUGE_VAL;
+}
+
+// After the residuals (Sec. 2.1): a band needs a correction unless its
+// eigenvalue moved by less than etol and its residual norm is below rtol; a
+// k with no such band is converged and frozen.  The bands that need one are
+// listed in map[k][0 .. nnc), and a k whose basis would outgrow nbmax (or
+// whose last block was dropped) restarts from its Ritz vectors (flag, nb =
+// nbnd).  One wave per k, lane j = band j.
+__global__ __launch_bounds__(64) void dav_decide_kernel(int nbnd, int nbmax, double etol, double rtol,
+                                                        const double* __restrict__ theta, const double* __restrict__ rn,
+                                                        double* th_old, int* active, int* nb, int* nnc, int* flag,
+                                                        int* map, int* force_restart, int* iters, int* nactive) {
+  const int k = blockIdx.x, j = threadIdx.x;
+  if (!active[k]) {
+    if (j == 0) {
+      nnc[k] = 0;
+      flag[k] = 0;
+    }
+    return;
+  }
+  const long o = (long)k * nbnd + j;
+  bool todo = false;
+  if (j < nbnd) {
+    const double th = theta[o];
+    todo = !(fabs(th - th_old[o]) < etol && rn[o] < rtol);
+    th_old[o] = th;
+  }
+  const unsigned long long m = __ballot(todo);
+  if (todo) map[(long)k * nbnd + __popcll(m & ((1ull << j) - 1ull))] = j;
+  if (j == 0) {
+    const int cnt = __popcll(m);
+    iters[k] += 1;
+    if (cnt == 0) {
+      active[k] = 0;
+      nnc[k] = 0;
+      flag[k] = 0;
+    } else {
+      atomicAdd(nactive, 1);
+      nnc[k] = cnt;
+      const int f = (nb[k] + cnt > nbmax) || force_restart[k];
+      flag[k] = f;
+      force_restart[k] = 0;
+      if (f) nb[k] = nbnd;
+    }
+  }
+}
+
+// A correction that lost nearly all of its norm to the projection (its
+// preconditioned residual lies in the basis, e.g. when H is diagonal in the
+// plane waves) is replaced by the residual itself, which is orthogonal to the
+// basis: mask[k][r] marks those rows, nrep[k] = nnc[k] where k has one (the
+// rows then projected again), else 0.
+__global__ __launch_bounds__(64) void dav_residual_mask_kernel(int nbnd, const double* __restrict__ n0,
+                                                               const double* __restrict__ n1, const int* nnc,
+                                                               int* mask, int* nrep) {
+  const int k = blockIdx.x, r = threadIdx.x;
+  bool m = false;
+  if (r < nbnd) {
+    const long o = (long)k * nbnd + r;
+    m = r < nnc[k] && !(n1[o] > 1e-8 * n0[o]);
+    mask[o] = m;
+  }
+  const unsigned long long b = __ballot(m);
+  if (r == 0) nrep[k] = b ? nnc[k] : 0;
+}
+
+// A block whose overlap is numerically singular drops its new rows; the k
+// restarts at its next iteration.
+__global__ void dav_chol_fail_kernel(int nk, const int* info, int* nnc, int* force_restart) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nk && info[k] && nnc[k] > 0) {
+    nnc[k] = 0;
+    force_restart[k] = 1;
+  }
+}
+
+// The new rows join the basis: nbo = old size (where they start), nb grows by
+// nnc; the Rayleigh-Ritz step works on nr = nb rows and forms ny = nbnd Ritz
+// vectors for the active k (0 for the frozen ones); hrows counts the rows H
+// was applied to.
+__global__ void dav_advance_kernel(int nk, int nbnd, int* nb, int* nbo, const int* nnc, const int* active, int* nr,
+                                   int* ny, long long* hrows) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nk) return;
+  const int b = nb[k], t = b + nnc[k];
+  nbo[k] = b;
+  nb[k] = t;
+  nr[k] = active[k] ? t : 0;
+  ny[k] = active[k] ? nbnd : 0;
+  hrows[k] += nnc[k];
+}
+
 }  // namespace
 
 pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, double tol_ry, int max_iter,
@@ -188,11 +299,14 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   const double rtol64 = 1e-5;
   const double tol32 = std::max(tol, 2e-6), rtol32 = 2e-4;
   const bool gen = c->have_q;  // generalized problem: S != 1
+  c->last_iterations = c->last_hpsi_kbands = c->last_graph_replays = 0;
   DevBufs b(c);
   cd *V, *HV, *X, *HX, *T, *Rb, *Hr, *Cr, *Om, *Sm, *Mm;
   cd *SV, *SX;
-  double *theta, *rn, *hd, *sd, *nrm0, *nrm1;
-  int *d_nb, *d_nnc, *d_map, *d_flag, *d_active, *d_info, *d_zero, *d_nr, *d_ny, *d_ntot, *d_mask;
+  double *theta, *rn, *hd, *sd, *nrm0, *nrm1, *th_old;
+  int *d_nb, *d_nbo, *d_nnc, *d_nrep, *d_map, *d_flag, *d_active, *d_info, *d_zero, *d_nr, *d_ny, *d_mask;
+  int *d_force, *d_iters, *d_nact;
+  long long* d_hrows;
   const size_t kb = (size_t)nk * nbmax * npwx, kn = (size_t)nk * nbnd * npwx;
   MKPW_TRY(b.get(kb, &V));
   MKPW_TRY(b.get(kb, &HV));
@@ -213,13 +327,16 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   MKPW_TRY(b.get((size_t)nk * nbnd * nbnd, &Sm));
   MKPW_TRY(b.get((size_t)nk * nbnd * nbnd, &Mm));
   MKPW_TRY(b.get((size_t)nk * nbnd, &theta));
+  MKPW_TRY(b.get((size_t)nk * nbnd, &th_old));
   MKPW_TRY(b.get((size_t)nk * nbnd, &rn));
   MKPW_TRY(b.get((size_t)nk * npwx, &hd));
   MKPW_TRY(b.get((size_t)nk * npwx, &sd));
   MKPW_TRY(b.get((size_t)nk * nbnd, &nrm0));
   MKPW_TRY(b.get((size_t)nk * nbnd, &nrm1));
   MKPW_TRY(b.get((size_t)nk, &d_nb));
+  MKPW_TRY(b.get((size_t)nk, &d_nbo));
   MKPW_TRY(b.get((size_t)nk, &d_nnc));
+  MKPW_TRY(b.get((size_t)nk, &d_nrep));
   MKPW_TRY(b.get((size_t)nk * nbnd, &d_map));
   MKPW_TRY(b.get((size_t)nk, &d_flag));
   MKPW_TRY(b.get((size_t)nk, &d_active));
@@ -227,35 +344,38 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   MKPW_TRY(b.get((size_t)nk, &d_zero));
   MKPW_TRY(b.get((size_t)nk, &d_nr));
   MKPW_TRY(b.get((size_t)nk, &d_ny));
-  MKPW_TRY(b.get((size_t)nk, &d_ntot));
   MKPW_TRY(b.get((size_t)nk * nbnd, &d_mask));
+  MKPW_TRY(b.get((size_t)nk, &d_force));
+  MKPW_TRY(b.get((size_t)nk, &d_iters));
+  MKPW_TRY(b.get((size_t)nk, &d_hrows));
+  MKPW_TRY(b.get((size_t)1, &d_nact));
   cplx<float>*T32 = nullptr, *HT32 = nullptr;
   if (prec == PW_MIXED) {
     MKPW_TRY(b.get(kn, &T32));
     MKPW_TRY(b.get(kn, &HT32));
   }
-  MKPW_HIP(c, hipMemsetAsync(d_zero, 0, sizeof(int) * nk, st));
+  const dim3 kgrid((nk + 255) / 256);
+  auto fill_i = [&](int* p, long n, int v) {
+    hipLaunchKernelGGL(fill_kernel<int>, dim3((unsigned)std::min<long>(1024, (n + 255) / 256)), dim3(256), 0, st, p,
+                       n, v);
+    return check_launch(c, "fill", st);
+  };
+  auto fill_c = [&](cd* p, long n) {
+    hipLaunchKernelGGL(fill_kernel<cd>, dim3((unsigned)std::min<long>(4096, (n + 255) / 256)), dim3(256), 0, st, p,
+                       n, cd{0.0, 0.0});
+    return check_launch(c, "fill", st);
+  };
+  MKPW_TRY(fill_i(d_zero, nk, 0));
+  MKPW_TRY(fill_i(d_iters, nk, 0));
+  hipLaunchKernelGGL(fill_kernel<long long>, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, st, d_hrows, (long)nk,
+                     0ll);
+  MKPW_TRY(check_launch(c, "fill", st));
 
-  // host mirrors
-  std::vector<int> nb(nk, 0), nnc(nk, nbnd), map((size_t)nk * nbnd), flag(nk, 0), active(nk, 1), info(nk, 0);
-  std::vector<double> th((size_t)nk * nbnd), th_old((size_t)nk * nbnd, std::numeric_limits<double>::infinity()),
-      rnh((size_t)nk * nbnd);
-  std::vector<int> iters(nk, 0);
-  std::vector<int> force_restart(nk, 0);
-  // uploads go through page-locked snapshots, so the host arrays may change
-  // right after a call; the per-k read-backs land in page-locked memory too
-  // (between two synchronisations an iteration uploads at most ten (nk) arrays
-  // and two (nk, nbnd) ones)
-  const size_t nkb = (size_t)nk * nbnd;
+  // read-back slots for the per-iteration count of active k-points
   HostStage hs(c, st);
-  MKPW_TRY(hs.init(sizeof(int) * (16 * (size_t)nk + 2 * nkb) + 256 * 24, sizeof(double) * 4 * nkb + sizeof(int) * nk));
-  double* p_th = hs.back<double>(0);
-  double* p_rn = p_th + nkb;
-  double* p_n0 = p_rn + nkb;
-  double* p_n1 = p_n0 + nkb;
-  int* p_info = reinterpret_cast<int*>(p_n1 + nkb);
-  auto h2d = [&](int* d, const std::vector<int>& h) { return hs.up(d, h.data(), h.size()); };
-  auto sync = [&]() { return hs.sync(); };
+  MKPW_TRY(hs.init(0, 2 * sizeof(int) + 256 + sizeof(int) * nk));
+  int* slot[2] = {hs.back<int>(0), hs.back<int>(sizeof(int))};
+  int* p_nnc = hs.back<int>(256);
 
   // diagonal of H for the preconditioner
   {
@@ -266,70 +386,70 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     MKPW_TRY(check_launch(c, "hdiag", st));
   }
 
-  // SV = S V on rows [nb, nb + nnc) (generalized problem only)
-  auto apply_s = [&](int nvec_max) -> pw_status {
-    if (!gen || nvec_max <= 0) return PW_OK;
+  // Every launch below takes its per-k sizes from device arrays and is sized
+  // for their largest possible values (nbnd new rows, nbmax basis rows), so
+  // the host never needs them; rows and k-points beyond the per-k counts idle.
+
+  // SV = S V on rows [nb, nb + cnt) (generalized problem only)
+  auto apply_s = [&](const int* cnt) -> pw_status {
+    if (!gen) return PW_OK;
     VecSel sel;
-    sel.nvec = nvec_max;
+    sel.nvec = nbnd;
     sel.kstride = (long)nbmax * npwx;
     sel.off = d_nb;
-    sel.cnt = d_nnc;
+    sel.cnt = cnt;
     return launch_spsi(c, PW_FP64, sel, V, SV, nullptr, 0.0, st);
   };
 
-  // apply H to rows [nb, nb + nnc) of V into HV (FP64 or complex64 staging)
+  // HV = H V on rows [nb, nb + nnc) (FP64, or complex64 through staging rows)
   bool fp64_h = (prec == PW_FP64);
-  auto apply_h = [&](int nvec_max) -> pw_status {
-    if (nvec_max <= 0) return PW_OK;
+  auto apply_h = [&]() -> pw_status {
     if (fp64_h) {
       VecSel sel;
-      sel.nvec = nvec_max;
+      sel.nvec = nbnd;
       sel.kstride = (long)nbmax * npwx;
       sel.off = d_nb;
       sel.cnt = d_nnc;
-      MKPW_TRY(launch_hpsi(c, PW_FP64, sel, V, HV, st));
-      return PW_OK;
+      return launch_hpsi(c, PW_FP64, sel, V, HV, st);
     }
-    MKPW_TRY(launch_to_c64(c, V, (long)nbmax * npwx, d_nb, T32, (long)nbnd * npwx, nullptr, d_nnc, nvec_max, st));
+    MKPW_TRY(launch_to_c64(c, V, (long)nbmax * npwx, d_nb, T32, (long)nbnd * npwx, nullptr, d_nnc, nbnd, st));
     VecSel sel;
-    sel.nvec = nvec_max;
+    sel.nvec = nbnd;
     sel.kstride = (long)nbnd * npwx;
     sel.cnt = d_nnc;
     MKPW_TRY(launch_hpsi(c, PW_MIXED, sel, T32, HT32, st));
-    MKPW_TRY(launch_to_c128(c, HT32, (long)nbnd * npwx, nullptr, HV, (long)nbmax * npwx, d_nb, d_nnc, nvec_max, st));
-    return PW_OK;
+    return launch_to_c128(c, HT32, (long)nbnd * npwx, nullptr, HV, (long)nbmax * npwx, d_nb, d_nnc, nbnd, st);
   };
 
-  // rows [nb, nb + nnc): remove the components along rows [0, nb) in the S
+  // rows [nb, nb + cnt): remove the components along rows [0, nb) in the S
   // inner product (twice) and normalise; the norms before (nrm0) and after
   // (nrm1) the projection are kept.  SV follows every row operation on V.
   cd* SV2 = gen ? SV : nullptr;
-  auto project = [&](int nb_max, int nnc_max) -> pw_status {
-    if (nnc_max <= 0) return PW_OK;
-    dim3 grid(nnc_max, nk);
-    hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, SV2, (long)nbmax * npwx, d_nb, d_nnc, npwx,
+  auto project = [&](const int* cnt) -> pw_status {
+    dim3 grid(nbnd, nk);
+    hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, SV2, (long)nbmax * npwx, d_nb, cnt, npwx,
                        nrm0, nbnd, 0);
     MKPW_TRY(check_launch(c, "norm", st));
-    for (int pass = 0; pass < 2 && nb_max > 0; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
       GramArgs g;
       g.A = SV; g.a_kstride = (long)nbmax * npwx; g.a_off = d_zero; g.a_cnt = d_nb;
-      g.B = V; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = d_nnc;
+      g.B = V; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = cnt;
       g.ld = npwx; g.npw = c->d_npw;
       g.C = Om; g.c_kstride = (long)nbmax * nbnd; g.ldc = nbnd;
-      MKPW_TRY(launch_gram(c, g, nb_max, nnc_max, st));
+      MKPW_TRY(launch_gram(c, g, nbmax, nbnd, st));
       CombArgs m;
       m.X = V; m.x_kstride = (long)nbmax * npwx; m.x_off = d_zero; m.x_cnt = d_nb;
-      m.Y = V; m.y_kstride = (long)nbmax * npwx; m.y_off = d_nb; m.y_cnt = d_nnc;
+      m.Y = V; m.y_kstride = (long)nbmax * npwx; m.y_off = d_nb; m.y_cnt = cnt;
       m.ld = npwx; m.Cm = Om; m.c_kstride = (long)nbmax * nbnd; m.ldc = nbnd;
       m.alpha = -1.0; m.accumulate = 1;
-      MKPW_TRY(launch_combine(c, m, nb_max, st));
+      MKPW_TRY(launch_combine(c, m, nbmax, st));
       if (gen) {
         m.X = SV;
         m.Y = SV;
-        MKPW_TRY(launch_combine(c, m, nb_max, st));
+        MKPW_TRY(launch_combine(c, m, nbmax, st));
       }
     }
-    hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, SV2, (long)nbmax * npwx, d_nb, d_nnc, npwx,
+    hipLaunchKernelGGL(normalize_rows_kernel, grid, dim3(256), 0, st, V, SV2, (long)nbmax * npwx, d_nb, cnt, npwx,
                        nrm1, nbnd, 1);
     return check_launch(c, "normalize", st);
   };
@@ -337,102 +457,62 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   // Cholesky-orthonormalise rows [nb, nb + nnc) among themselves in the S inner
   // product (twice); a k whose block is numerically dependent drops its new rows
   // and restarts next time
-  auto cholqr = [&](int nnc_max) -> pw_status {
-    if (nnc_max <= 0) return PW_OK;
+  auto cholqr = [&]() -> pw_status {
     for (int pass = 0; pass < 2; ++pass) {
       GramArgs g;
       g.A = V; g.a_kstride = (long)nbmax * npwx; g.a_off = d_nb; g.a_cnt = d_nnc;
       g.B = SV; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = d_nnc;
       g.ld = npwx; g.npw = c->d_npw;
       g.C = Sm; g.c_kstride = (long)nbnd * nbnd; g.ldc = nbnd;
-      MKPW_TRY(launch_gram(c, g, nnc_max, nnc_max, st));
+      MKPW_TRY(launch_gram(c, g, nbnd, nbnd, st));
       MKPW_TRY(launch_chol_inv(c, Sm, (long)nbnd * nbnd, nbnd, d_nnc, Mm, (long)nbnd * nbnd, nbnd, d_info, st));
+      hipLaunchKernelGGL(dav_chol_fail_kernel, kgrid, dim3(256), 0, st, nk, d_info, d_nnc, d_force);
+      MKPW_TRY(check_launch(c, "chol_fail", st));
       MKPW_TRY(launch_trmm(c, V, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
       if (gen) MKPW_TRY(launch_trmm(c, SV, (long)nbmax * npwx, d_nb, d_nnc, Mm, (long)nbnd * nbnd, nbnd, st));
-      MKPW_HIP(c, hipMemcpyAsync(p_info, d_info, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
-      MKPW_HIP(c, sync());
-      std::memcpy(info.data(), p_info, sizeof(int) * nk);
-      bool changed = false;
-      for (int k = 0; k < nk; ++k)
-        if (info[k] && nnc[k] > 0) {
-          nnc[k] = 0;
-          force_restart[k] = 1;
-          changed = true;
-        }
-      if (changed) MKPW_HIP(c, h2d(d_nnc, nnc));
     }
     return PW_OK;
   };
 
-  // new basis rows from the corrections; a correction that loses nearly all of
-  // its norm to the projection (the preconditioned residual lies in the basis,
-  // e.g. when H is diagonal in the plane waves) is replaced by the residual
-  // itself, which is orthogonal to the basis by construction
-  std::vector<double> n0h((size_t)nk * nbnd), n1h((size_t)nk * nbnd);
-  std::vector<int> mask((size_t)nk * nbnd);
-  auto orthonormalize = [&](int nb_max, int nnc_max, bool allow_residual) -> pw_status {
-    if (nnc_max <= 0) return PW_OK;
-    MKPW_TRY(project(nb_max, nnc_max));
+  // new basis rows from the corrections, with the residual in place of a
+  // correction that the projection annihilates
+  auto orthonormalize = [&](bool allow_residual) -> pw_status {
+    MKPW_TRY(project(d_nnc));
     if (allow_residual) {
-      MKPW_HIP(c, hipMemcpyAsync(p_n0, nrm0, sizeof(double) * nkb, hipMemcpyDeviceToHost, st));
-      MKPW_HIP(c, hipMemcpyAsync(p_n1, nrm1, sizeof(double) * nkb, hipMemcpyDeviceToHost, st));
-      MKPW_HIP(c, sync());
-      std::memcpy(n0h.data(), p_n0, sizeof(double) * nkb);
-      std::memcpy(n1h.data(), p_n1, sizeof(double) * nkb);
-      bool any = false;
-      for (int k = 0; k < nk; ++k)
-        for (int r = 0; r < nbnd; ++r) {
-          const size_t o = (size_t)k * nbnd + r;
-          mask[o] = (r < nnc[k]) && !(n1h[o] > 1e-8 * n0h[o]);
-          any = any || mask[o];
-        }
-      if (any) {
-        MKPW_HIP(c, h2d(d_mask, mask));
-        dim3 grid((npwx + 255) / 256, nk, nnc_max);
-        hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(256), 0, st, Rb, nbnd, V, nbmax, d_nb, d_nnc, d_map, npwx,
-                           d_mask);
-        MKPW_TRY(check_launch(c, "gather_r", st));
-        MKPW_TRY(apply_s(nnc_max));
-        MKPW_TRY(project(nb_max, nnc_max));
-      }
+      hipLaunchKernelGGL(dav_residual_mask_kernel, dim3(nk), dim3(64), 0, st, nbnd, nrm0, nrm1, d_nnc, d_mask, d_nrep);
+      MKPW_TRY(check_launch(c, "residual_mask", st));
+      dim3 grid((npwx + 255) / 256, nk, nbnd);
+      hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(256), 0, st, Rb, nbnd, V, nbmax, d_nb, d_nrep, d_map, npwx,
+                         d_mask);
+      MKPW_TRY(check_launch(c, "gather_r", st));
+      MKPW_TRY(apply_s(d_nrep));
+      MKPW_TRY(project(d_nrep));
     }
-    return cholqr(nnc_max);
+    return cholqr();
   };
 
-  // extend H~: rows [0, nb + nnc) x cols [nb, nb + nnc) = V^H HV_new (+ mirror)
-  auto extend_h = [&](int ntot_max, int nnc_max) -> pw_status {
-    std::vector<int> ntot(nk);
-    for (int k = 0; k < nk; ++k) ntot[k] = nb[k] + nnc[k];
-    MKPW_HIP(c, h2d(d_ntot, ntot));
+  // the new rows join the basis; extend H~ by rows [0, nb) x cols [nbo, nb) =
+  // V^H HV_new (and the mirrored entries); diagonalise; X = V C, HX = HV C (and
+  // S X) for the active k-points (the others keep their converged Ritz pairs)
+  auto extend_and_ritz = [&]() -> pw_status {
+    hipLaunchKernelGGL(dav_advance_kernel, kgrid, dim3(256), 0, st, nk, nbnd, d_nb, d_nbo, d_nnc, d_active, d_nr, d_ny,
+                       d_hrows);
+    MKPW_TRY(check_launch(c, "advance", st));
     GramArgs g;
-    g.A = V; g.a_kstride = (long)nbmax * npwx; g.a_off = d_zero; g.a_cnt = d_ntot;
-    g.B = HV; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nb; g.b_cnt = d_nnc;
+    g.A = V; g.a_kstride = (long)nbmax * npwx; g.a_off = d_zero; g.a_cnt = d_nb;
+    g.B = HV; g.b_kstride = (long)nbmax * npwx; g.b_off = d_nbo; g.b_cnt = d_nnc;
     g.ld = npwx; g.npw = c->d_npw;
-    g.C = Hr; g.c_kstride = (long)nbmax * nbmax; g.ldc = nbmax; g.c_roff = d_zero; g.c_coff = d_nb;
+    g.C = Hr; g.c_kstride = (long)nbmax * nbmax; g.ldc = nbmax; g.c_roff = d_zero; g.c_coff = d_nbo;
     g.mirror = 1;
-    MKPW_TRY(launch_gram(c, g, ntot_max, nnc_max, st));
-    return PW_OK;
-  };
-
-  std::vector<int> nr(nk), ny(nk);
-  auto ritz = [&](int nb_max) -> pw_status {
-    // nb := nb + nnc has been applied; diagonalise and form X, HX for the
-    // active k-points (the others keep their converged Ritz pairs)
-    for (int k = 0; k < nk; ++k) {
-      nr[k] = active[k] ? nb[k] : 0;
-      ny[k] = active[k] ? nbnd : 0;
-    }
-    MKPW_HIP(c, h2d(d_nb, nb));
-    MKPW_HIP(c, h2d(d_nr, nr));
-    MKPW_HIP(c, h2d(d_ny, ny));
-    MKPW_TRY(launch_heev(c, Hr, (long)nbmax * nbmax, nbmax, d_nr, nb_max, nbnd, theta, Cr, (long)nbmax * nbnd, nbnd, st));
+    MKPW_TRY(launch_gram(c, g, nbmax, nbnd, st));
+    MKPW_TRY(launch_heev(c, Hr, (long)nbmax * nbmax, nbmax, d_nr, nbmax, nbnd, theta, Cr, (long)nbmax * nbnd, nbnd, st));
     for (int which = 0; which < 2; ++which) {
       CombArgs m;
       m.X = which ? HV : V; m.x_kstride = (long)nbmax * npwx; m.x_cnt = d_nr;
       m.Y = which ? HX : X; m.y_kstride = (long)nbnd * npwx; m.y_n = nbnd;
       m.y_cnt = d_ny;
       m.ld = npwx; m.Cm = Cr; m.c_kstride = (long)nbmax * nbnd; m.ldc = nbnd;
-      MKPW_TRY(launch_combine(c, m, nb_max, st));
+      MKPW_TRY(launch_combine(c, m, nbmax, st));
     }
     if (gen) {
       // S X afresh rather than SV C: the S-images carried along with the basis
@@ -447,146 +527,180 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
     return PW_OK;
   };
 
-  // ---- start: V[0:nbnd] = psi, orthonormalise, H V, H~, Ritz pairs
-  {
-    dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
-    hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, psi, nbnd, V, nbmax, nbnd, npwx);
-    MKPW_TRY(check_launch(c, "copy", st));
-    std::fill(nb.begin(), nb.end(), 0);
-    std::fill(nnc.begin(), nnc.end(), nbnd);
-    MKPW_HIP(c, h2d(d_nb, nb));
-    MKPW_HIP(c, h2d(d_nnc, nnc));
-    MKPW_TRY(apply_s(nbnd));
-    MKPW_TRY(orthonormalize(0, nbnd, false));
-    for (int k = 0; k < nk; ++k)
-      if (nnc[k] == 0) return set_err(c, PW_EINVAL,
-                       std::string("starting vectors are linearly dependent") +
-                           (gen ? " (or S is not positive definite)" : "") + " at k " + std::to_string(k));
-    MKPW_TRY(apply_h(nbnd));
-    MKPW_HIP(c, hipMemsetAsync(Hr, 0, sizeof(cd) * (size_t)nk * nbmax * nbmax, st));
-    MKPW_TRY(extend_h(nbnd, nbnd));
-    for (int k = 0; k < nk; ++k) nb[k] = nbnd;
-    MKPW_TRY(ritz(nbnd));
-  }
-
-  bool refine = false;  // mixed precision: FP64 phase started
-  int it = 0;
-  bool all_done = false;
-  for (it = 1; it <= max_iter; ++it) {
-    // residuals of the current Ritz pairs
-    MKPW_HIP(c, h2d(d_active, active));
+  // one iteration: residuals, the device-side decisions, restarts, corrections,
+  // orthonormalisation, H on the new rows, Rayleigh-Ritz
+  auto iteration = [&](double etol, double rtol) -> pw_status {
+    MKPW_TRY(fill_i(d_nact, 1, 0));
     {
       dim3 grid(nbnd, nk);
       hipLaunchKernelGGL(resid_kernel, grid, dim3(256), 0, st, SX, HX, theta, d_active, hd, sd, c->d_npw, npwx, nbnd,
                          T, Rb, rn);
       MKPW_TRY(check_launch(c, "resid", st));
     }
-    MKPW_HIP(c, hipMemcpyAsync(p_th, theta, sizeof(double) * nkb, hipMemcpyDeviceToHost, st));
-    MKPW_HIP(c, hipMemcpyAsync(p_rn, rn, sizeof(double) * nkb, hipMemcpyDeviceToHost, st));
-    MKPW_HIP(c, sync());
-    std::memcpy(th.data(), p_th, sizeof(double) * nkb);
-    std::memcpy(rnh.data(), p_rn, sizeof(double) * nkb);
-    const double etol = fp64_h ? tol : tol32, rtol = fp64_h ? rtol64 : rtol32;
-    int n_active = 0, nnc_max = 0, nb_max = 0;
-    for (int k = 0; k < nk; ++k) {
-      if (!active[k]) {
-        nnc[k] = 0;
-        flag[k] = 0;
-        continue;
-      }
-      iters[k] = it;
-      int cnt = 0;
-      for (int j = 0; j < nbnd; ++j) {
-        const size_t o = (size_t)k * nbnd + j;
-        bool ok = std::fabs(th[o] - th_old[o]) < etol && rnh[o] < rtol;
-        if (!ok) map[(size_t)k * nbnd + cnt++] = j;
-      }
-      if (cnt == 0) {
-        active[k] = 0;
-        nnc[k] = 0;
-        flag[k] = 0;
-        continue;
-      }
-      ++n_active;
-      nnc[k] = cnt;
-      flag[k] = (nb[k] + cnt > nbmax) || force_restart[k];
-      force_restart[k] = 0;
-      if (flag[k]) nb[k] = nbnd;
-      nnc_max = std::max(nnc_max, cnt);
-      nb_max = std::max(nb_max, nb[k] + cnt);
-    }
-    th_old = th;
-    if (n_active == 0) {
-      if (prec == PW_MIXED && !refine) {
-        // FP64 refinement: restart every k from its Ritz vectors with H in FP64
-        refine = true;
-        fp64_h = true;
-        std::fill(active.begin(), active.end(), 1);
-        std::fill(th_old.begin(), th_old.end(), std::numeric_limits<double>::infinity());
-        dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
-        hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, X, nbnd, V, nbmax, nbnd, npwx);
-        MKPW_TRY(check_launch(c, "copy", st));
-        if (gen) {
-          hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, SX, nbnd, SV, nbmax, nbnd, npwx);
-          MKPW_TRY(check_launch(c, "copy", st));
-        }
-        std::fill(nb.begin(), nb.end(), 0);
-        std::fill(nnc.begin(), nnc.end(), nbnd);
-        MKPW_HIP(c, h2d(d_nb, nb));
-        MKPW_HIP(c, h2d(d_nnc, nnc));
-        MKPW_TRY(apply_h(nbnd));
-        MKPW_HIP(c, hipMemsetAsync(Hr, 0, sizeof(cd) * (size_t)nk * nbmax * nbmax, st));
-        MKPW_TRY(extend_h(nbnd, nbnd));
-        for (int k = 0; k < nk; ++k) nb[k] = nbnd;
-        MKPW_TRY(ritz(nbnd));
-        continue;
-      }
-      all_done = true;
-      break;
-    }
-    MKPW_HIP(c, h2d(d_flag, flag));
-    MKPW_HIP(c, h2d(d_map, map));
-    MKPW_HIP(c, h2d(d_nnc, nnc));
+    hipLaunchKernelGGL(dav_decide_kernel, dim3(nk), dim3(64), 0, st, nbnd, nbmax, etol, rtol, theta, rn, th_old,
+                       d_active, d_nb, d_nnc, d_flag, d_map, d_force, d_iters, d_nact);
+    MKPW_TRY(check_launch(c, "decide", st));
     {
       dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
       hipLaunchKernelGGL(restart_kernel, grid, dim3(256), 0, st, d_flag, X, HX, gen ? SX : nullptr, V, HV, SV, nbnd,
                          nbmax, npwx, Hr, theta);
       MKPW_TRY(check_launch(c, "restart", st));
     }
-    MKPW_HIP(c, h2d(d_nb, nb));
     {
-      dim3 grid((npwx + 255) / 256, nk, nnc_max);
+      dim3 grid((npwx + 255) / 256, nk, nbnd);
       hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(256), 0, st, T, nbnd, V, nbmax, d_nb, d_nnc, d_map, npwx,
                          (const int*)nullptr);
       MKPW_TRY(check_launch(c, "gather", st));
     }
-    MKPW_TRY(apply_s(nnc_max));
-    int nb_cur_max = 0;
-    for (int k = 0; k < nk; ++k) nb_cur_max = std::max(nb_cur_max, nb[k]);
-    MKPW_TRY(orthonormalize(nb_cur_max, nnc_max, true));
-    MKPW_TRY(apply_h(nnc_max));
-    MKPW_TRY(extend_h(nb_max, nnc_max));
-    int ntot_max = 0;
-    for (int k = 0; k < nk; ++k) {
-      nb[k] += nnc[k];
-      ntot_max = std::max(ntot_max, nb[k]);
-    }
-    MKPW_TRY(ritz(ntot_max));
-  }
+    MKPW_TRY(apply_s(d_nnc));
+    MKPW_TRY(orthonormalize(true));
+    MKPW_TRY(apply_h());
+    return extend_and_ritz();
+  };
 
-  // results: Ritz vectors and values
+  // (re)start every k from the nbnd rows in V[0:nbnd] (and SV when `have_sv`):
+  // orthonormalise them unless they already are, H on them, Rayleigh-Ritz
+  auto start = [&](bool orthonormal) -> pw_status {
+    hipLaunchKernelGGL(dav_reset_kernel, kgrid, dim3(256), 0, st, nk, nbnd, d_nb, d_nnc, d_active, d_force, th_old);
+    MKPW_TRY(check_launch(c, "reset", st));
+    if (!orthonormal) {
+      MKPW_TRY(apply_s(d_nnc));
+      MKPW_TRY(orthonormalize(false));
+      MKPW_HIP(c, hipMemcpyAsync(p_nnc, d_nnc, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
+      MKPW_HIP(c, hipStreamSynchronize(st));
+      for (int k = 0; k < nk; ++k)
+        if (p_nnc[k] == 0)
+          return set_err(c, PW_EINVAL,
+                         std::string("starting vectors are linearly dependent") +
+                             (gen ? " (or S is not positive definite)" : "") + " at k " + std::to_string(k));
+    }
+    MKPW_TRY(apply_h());
+    MKPW_TRY(fill_c(Hr, (long)nk * nbmax * nbmax));
+    return extend_and_ritz();
+  };
+
+  // ---- start: V[0:nbnd] = psi
+  {
+    dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
+    hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, psi, nbnd, V, nbmax, nbnd, npwx);
+    MKPW_TRY(check_launch(c, "copy", st));
+  }
+  MKPW_TRY(start(false));
+
+  // ---- iterations.  The host learns whether any k is still active one
+  // iteration late (the count is copied to page-locked memory behind each
+  // iteration and read once the next one is queued), so the device never
+  // waits for it; an iteration queued after every k has converged changes
+  // nothing.  From the second iteration of a phase on, the iteration runs as
+  // a captured graph, replayed.
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct Cleanup {
+    hipEvent_t* e;
+    hipGraph_t* g;
+    hipGraphExec_t* x;
+    ~Cleanup() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+      if (*x) (void)hipGraphExecDestroy(*x);
+      if (*g) (void)hipGraphDestroy(*g);
+    }
+  } cleanup{ev, &graph, &exec};
+  for (int i = 0; i < 2; ++i) MKPW_HIP(c, hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+  bool use_graph = c->solver_graph && !c->trace;
+  auto drop_graph = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  };
+  auto run_iteration = [&](int in_phase, double etol, double rtol) -> pw_status {
+    if (use_graph && in_phase >= 2) {
+      if (!exec) {
+        bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+          pw_status s = iteration(etol, rtol);
+          hipGraph_t g = nullptr;
+          const bool ended = hipStreamEndCapture(st, &g) == hipSuccess;
+          if (s != PW_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+          }
+          ok = ended && g && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+          graph = g;
+        }
+        if (!ok) {  // run this and every later iteration launch by launch
+          (void)hipGetLastError();
+          drop_graph();
+          use_graph = false;
+          return iteration(etol, rtol);
+        }
+      }
+      MKPW_HIP(c, hipGraphLaunch(exec, st));
+      ++c->last_graph_replays;
+      return PW_OK;
+    }
+    return iteration(etol, rtol);
+  };
+
+  bool refine = false;  // mixed precision: FP64 phase started
+  bool all_done = false;
+  int phase_first = 1;  // first iteration of the current phase
+  int it = 0;
+  for (it = 1;; ++it) {
+    if (it <= max_iter) {
+      const double etol = fp64_h ? tol : tol32, rtol = fp64_h ? rtol64 : rtol32;
+      MKPW_TRY(run_iteration(it - phase_first + 1, etol, rtol));
+      MKPW_HIP(c, hipMemcpyAsync(slot[it & 1], d_nact, sizeof(int), hipMemcpyDeviceToHost, st));
+      MKPW_HIP(c, hipEventRecord(ev[it & 1], st));
+    }
+    if (it > phase_first) {
+      MKPW_HIP(c, hipEventSynchronize(ev[(it - 1) & 1]));
+      if (*slot[(it - 1) & 1] == 0) {
+        if (prec == PW_MIXED && !refine && c->mixed_refine) {
+          // FP64 refinement: restart every k from its Ritz vectors with H in FP64
+          refine = true;
+          fp64_h = true;
+          drop_graph();
+          dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
+          hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, X, nbnd, V, nbmax, nbnd, npwx);
+          MKPW_TRY(check_launch(c, "copy", st));
+          if (gen) {
+            hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, SX, nbnd, SV, nbmax, nbnd, npwx);
+            MKPW_TRY(check_launch(c, "copy", st));
+          }
+          MKPW_TRY(start(true));
+          phase_first = it + 1;
+          continue;
+        }
+        all_done = true;
+        break;
+      }
+    }
+    if (it > max_iter) break;
+  }
+  c->last_iterations = std::min(it, max_iter);
+
+  // results: Ritz vectors and values, per-k counts
   {
     dim3 grid(std::max(1, std::min(64, (nbnd * npwx + 255) / 256)), nk);
     hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, st, X, nbnd, psi, nbnd, nbnd, npwx);
     MKPW_TRY(check_launch(c, "copy", st));
   }
+  std::vector<int> iters(nk), active(nk);
+  std::vector<long long> hrows(nk);
   MKPW_HIP(c, hipMemcpyAsync(eig, theta, sizeof(double) * (size_t)nk * nbnd, hipMemcpyDeviceToHost, st));
-  MKPW_HIP(c, sync());
+  MKPW_HIP(c, hipMemcpyAsync(iters.data(), d_iters, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
+  MKPW_HIP(c, hipMemcpyAsync(active.data(), d_active, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
+  MKPW_HIP(c, hipMemcpyAsync(hrows.data(), d_hrows, sizeof(long long) * nk, hipMemcpyDeviceToHost, st));
+  MKPW_HIP(c, hipStreamSynchronize(st));
   bool all_conv = true;
   for (int k = 0; k < nk; ++k) {
     if (iters_out) iters_out[k] = iters[k];
     if (conv_out) conv_out[k] = active[k] ? 0 : 1;
     if (active[k]) all_conv = false;
+    c->last_hpsi_kbands += hrows[k];
   }
   if (!all_done || !all_conv) return set_err(c, PW_ENOCONV, "Davidson: some k-points did not converge");
   return PW_OK;

@@ -527,7 +527,7 @@ constexpr bool allow_512() {
 }
 template <class T, int N, int VARIANT>
 constexpr bool allow_1024() {
-  return sizeof(T) == 4 ? (VARIANT != 1 || N <= 20) : (VARIANT == 2 && N <= 24);
+  return sizeof(T) == 4 ? (VARIANT != 1 || N <= 20) : VARIANT == 2;
 }
 
 template <class T, int N, int WC, int VARIANT>

@@ -111,6 +111,11 @@ struct pw_ctx {
   int64_t hpsi_slab = 0;     // 0 = autotuned, else z planes per slab
   int64_t hpsi_threads = 0;  // 0 = autotuned, else work-items per workgroup
   int64_t tune_log = 0;      // print the autotuning timings to stderr
+  int64_t solver_graph = 1;  // replay one solver iteration as a captured HIP graph
+  int64_t mixed_refine = 1;  // mixed-precision Davidson: refine in FP64 after the complex64 phase
+  // statistics of the last solver call: iterations run, and k-band rows H was
+  // applied to (each (k, vector) row counted once per application)
+  int64_t last_iterations = 0, last_hpsi_kbands = 0, last_graph_replays = 0;
   int last_hpsi_variant = 0, last_hpsi_slab = 0, last_hpsi_threads = 0;  // shape of the last H|psi> launch
 
   // crystal and basis

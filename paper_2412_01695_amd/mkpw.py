@@ -91,6 +91,42 @@ def _ptr(x):
     raise TypeError(f"cannot take a pointer of {type(x)}")
 
 
+def _dims(ctx):
+    """The context's sizes as the library reports them (nk, npwx, nproj, mesh)."""
+    g = lambda k: pw_get_option(ctx, k)
+    return {"nk": g("nk"), "npwx": g("npwx"), "nproj": g("nproj"), "fft": (g("fft1"), g("fft2"), g("fft3"))}
+
+
+_C128, _C64 = "complex128", "complex64"
+
+
+def _dev(x, name, shape, dtype):
+    """Check a device array before its pointer crosses the ABI: a torch tensor
+    must live on the GPU, be contiguous and have exactly this dtype and shape.
+    A bare integer is taken as a raw device pointer that the caller vouches
+    for (nothing can be checked)."""
+    if isinstance(x, int):
+        return x
+    if not hasattr(x, "data_ptr"):
+        raise TypeError(f"{name}: expected a device tensor or a raw pointer, got {type(x).__name__}")
+    if getattr(x, "device", None) is None or x.device.type != "cuda":
+        raise ValueError(f"{name}: must be a GPU tensor (got device {getattr(x, 'device', None)})")
+    if str(x.dtype).replace("torch.", "") != dtype:
+        raise ValueError(f"{name}: dtype must be {dtype}, got {str(x.dtype).replace('torch.', '')}")
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape must be {tuple(shape)}, got {tuple(x.shape)}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return x.data_ptr()
+
+
+def _host(a, name, shape, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if a.size != int(np.prod(shape)):
+        raise ValueError(f"{name}: expected {int(np.prod(shape))} values {tuple(shape)}, got {a.size}")
+    return a
+
+
 def _dbl(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data_as(_pd)
@@ -117,6 +153,7 @@ def pw_create(hip_device: int = 0, hip_stream=None):
 
 
 def pw_destroy(ctx):
+    _npw_of.pop(getattr(ctx, "value", None), None)
     _lib.pw_destroy(ctx)
 
 
@@ -135,6 +172,7 @@ def pw_get_option(ctx, key: str) -> int:
 
 
 def pw_set_lattice(ctx, a):
+    _npw_of.pop(ctx.value, None)  # the basis is reset
     a, p = _dbl(np.asarray(a).reshape(9))
     return _check(ctx, _lib.pw_set_lattice(ctx, p))
 
@@ -144,34 +182,70 @@ def pw_set_cutoff(ctx, ecut_ry: float, fft=(0, 0, 0)):
     return _check(ctx, _lib.pw_set_cutoff(ctx, float(ecut_ry), p))
 
 
+# npw per k-point of each context whose k-points were set through this module
+# (keyed by the context's address), so that the Miller read-backs are sized by
+# what the library will write, not by what the caller says
+_npw_of = {}
+
+
 def pw_set_kpoints(ctx, k_cart):
     k, p = _dbl(np.asarray(k_cart).reshape(-1, 3))
     nk = k.shape[0]
     npw = np.zeros(nk, dtype=np.int32)
     npwx = np.zeros(1, dtype=np.int32)
+    _npw_of.pop(ctx.value, None)
     _check(ctx, _lib.pw_set_kpoints(ctx, nk, p, npw.ctypes.data_as(_pi), npwx.ctypes.data_as(_pi)))
+    _npw_of[ctx.value] = npw.copy()
     return npw, int(npwx[0])
 
 
-def pw_get_miller(ctx, ik: int, npw: int):
-    m = np.zeros((npw, 3), dtype=np.int32)
+def _known_npw(ctx):
+    npw = _npw_of.get(ctx.value)
+    if npw is None or npw.size != _dims(ctx)["nk"]:
+        raise ValueError("the context's k-points were not set through this binding; their basis sizes are unknown")
+    return npw
+
+
+def pw_get_miller(ctx, ik: int, npw: int | None = None):
+    """Miller indices (npw[ik], 3) of k-point ik; npw, if given, must match."""
+    known = _known_npw(ctx)
+    if not 0 <= int(ik) < known.size:
+        raise ValueError(f"ik = {ik} outside [0, {known.size})")
+    if npw is not None and int(npw) != int(known[ik]):
+        raise ValueError(f"npw = {npw} but k-point {ik} has {int(known[ik])} plane waves")
+    m = np.zeros((int(known[ik]), 3), dtype=np.int32)
     _check(ctx, _lib.pw_get_miller(ctx, int(ik), m.ctypes.data_as(_pi)))
     return m
 
 
-def pw_get_miller_all(ctx, npw):
-    """Every k's Miller list, concatenated (sum(npw), 3)."""
-    m = np.zeros((int(np.sum(npw)), 3), dtype=np.int32)
+def pw_get_miller_all(ctx, npw=None):
+    """Every k's Miller list, concatenated (sum(npw), 3); npw, if given, must match."""
+    known = _known_npw(ctx)
+    if npw is not None and not np.array_equal(np.asarray(npw), known):
+        raise ValueError("npw does not match the context's basis sizes")
+    m = np.zeros((int(np.sum(known)), 3), dtype=np.int32)
     _check(ctx, _lib.pw_get_miller(ctx, -1, m.ctypes.data_as(_pi)))
     return m
 
 
+def _rows(ctx, nvec):
+    d = _dims(ctx)
+    return (d["nk"], int(nvec), d["npwx"])
+
+
+def _wf(prec):
+    return _C128 if int(prec) == PW_FP64 else _C64
+
+
 def pw_init_guess(ctx, nbnd: int, seed: int, psi):
-    return _check(ctx, _lib.pw_init_guess(ctx, int(nbnd), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(psi)))
+    """psi: device complex128 (nk, nbnd, npwx)."""
+    p = _dev(psi, "psi", _rows(ctx, nbnd), _C128)
+    return _check(ctx, _lib.pw_init_guess(ctx, int(nbnd), int(seed) & 0xFFFFFFFFFFFFFFFF, p))
 
 
 def pw_set_vloc(ctx, v_r):
-    v, p = _dbl(v_r)
+    """v_r: host real (N1, N2, N3), Ha."""
+    v, p = _dbl(_host(v_r, "v_r", _dims(ctx)["fft"], np.float64))
     return _check(ctx, _lib.pw_set_vloc(ctx, p))
 
 
@@ -180,6 +254,12 @@ def pw_set_projectors(ctx, beta, dij):
     beta = np.ascontiguousarray(beta, dtype=np.complex128)
     dij = np.ascontiguousarray(dij, dtype=np.complex128)
     nproj = beta.shape[1] if beta.ndim == 3 else 0
+    if nproj:
+        d = _dims(ctx)
+        if beta.shape != (d["nk"], nproj, d["npwx"]):
+            raise ValueError(f"beta: shape must be ({d['nk']}, nproj, {d['npwx']}), got {beta.shape}")
+        if dij.shape != (nproj, nproj):
+            raise ValueError(f"dij: shape must be ({nproj}, {nproj}), got {dij.shape}")
     return _check(ctx, _lib.pw_set_projectors(ctx, nproj, beta.ctypes.data if nproj else None,
                                               dij.ctypes.data if nproj else None))
 
@@ -188,24 +268,40 @@ def pw_set_qij(ctx, qij):
     """qij: host complex128 (nproj, nproj), or None to remove the overlap."""
     if qij is None:
         return _check(ctx, _lib.pw_set_qij(ctx, None))
+    n = _dims(ctx)["nproj"]
     q = np.ascontiguousarray(qij, dtype=np.complex128)
+    if n:  # without projectors the library refuses the call (PW_ESTATE) before reading q
+        q = _host(q, "qij", (n, n), np.complex128)
     return _check(ctx, _lib.pw_set_qij(ctx, q.ctypes.data))
 
 
 def pw_h_psi(ctx, prec: int, nbnd: int, psi, hpsi):
-    return _check(ctx, _lib.pw_h_psi(ctx, int(prec), int(nbnd), _ptr(psi), _ptr(hpsi)))
+    """psi, hpsi: device (nk, nbnd, npwx), complex128 (PW_FP64) or complex64 (PW_MIXED)."""
+    shape, dt = _rows(ctx, nbnd), _wf(prec)
+    p, h = _dev(psi, "psi", shape, dt), _dev(hpsi, "hpsi", shape, dt)
+    return _check(ctx, _lib.pw_h_psi(ctx, int(prec), int(nbnd), p, h))
 
 
 def pw_s_psi(ctx, prec: int, nbnd: int, psi, spsi):
-    return _check(ctx, _lib.pw_s_psi(ctx, int(prec), int(nbnd), _ptr(psi), _ptr(spsi)))
+    """psi, spsi: device (nk, nbnd, npwx), complex128 (PW_FP64) or complex64 (PW_MIXED)."""
+    shape, dt = _rows(ctx, nbnd), _wf(prec)
+    p, s = _dev(psi, "psi", shape, dt), _dev(spsi, "spsi", shape, dt)
+    return _check(ctx, _lib.pw_s_psi(ctx, int(prec), int(nbnd), p, s))
 
 
-def pw_davidson(ctx, prec: int, nbnd: int, psi, nk: int, tol_ry: float, max_iter: int):
-    """Returns (status, eig (nk, nbnd) Ha, iters (nk), converged (nk))."""
+def pw_davidson(ctx, prec: int, nbnd: int, psi, nk: int | None, tol_ry: float, max_iter: int):
+    """psi: device complex128 (nk, nbnd, npwx), guess in, eigenvectors out.
+    nk, if given, must be the context's k-point count.
+    Returns (status, eig (nk, nbnd) Ha, iters (nk), converged (nk))."""
+    shape = _rows(ctx, nbnd)
+    if nk is not None and int(nk) != shape[0]:
+        raise ValueError(f"nk = {nk} but the context holds {shape[0]} k-points")
+    nk = shape[0]
+    p = _dev(psi, "psi", shape, _C128)
     eig = np.zeros((nk, nbnd), dtype=np.float64)
     iters = np.zeros(nk, dtype=np.int32)
     conv = np.zeros(nk, dtype=np.int32)
-    st = _lib.pw_davidson(ctx, int(prec), int(nbnd), _ptr(psi), eig.ctypes.data_as(_pd), float(tol_ry),
+    st = _lib.pw_davidson(ctx, int(prec), int(nbnd), p, eig.ctypes.data_as(_pd), float(tol_ry),
                           int(max_iter), iters.ctypes.data_as(_pi), conv.ctypes.data_as(_pi))
     _check(ctx, st, allow_noconv=True)
     return st, eig, iters, conv
@@ -213,23 +309,38 @@ def pw_davidson(ctx, prec: int, nbnd: int, psi, nk: int, tol_ry: float, max_iter
 
 def pw_dfpt_cg(ctx, prec: int, nocc: int, psi_occ, eps_ha, alpha_ha, nrhs: int, rhs, dpsi, thr: float,
                max_iter: int):
-    """Returns (status, iters (nk*nrhs))."""
-    eps, pe = _dbl(eps_ha)
-    alpha, pa = _dbl(alpha_ha)
-    iters = np.zeros(eps.size, dtype=np.int32)
-    st = _lib.pw_dfpt_cg(ctx, int(prec), int(nocc), _ptr(psi_occ), pe, pa, int(nrhs), _ptr(rhs), _ptr(dpsi),
-                         float(thr), int(max_iter), iters.ctypes.data_as(_pi))
+    """psi_occ: device complex128 (nk, nocc, npwx); eps_ha: host (nk, nrhs);
+    alpha_ha: host (nk); rhs, dpsi: device complex128 (nk, nrhs, npwx).
+    Returns (status, iters (nk*nrhs))."""
+    nk = _dims(ctx)["nk"]
+    eps, pe = _dbl(_host(eps_ha, "eps_ha", (nk, nrhs), np.float64))
+    alpha, pa = _dbl(_host(alpha_ha, "alpha_ha", (nk,), np.float64))
+    pu = _dev(psi_occ, "psi_occ", _rows(ctx, nocc), _C128)
+    pr = _dev(rhs, "rhs", _rows(ctx, nrhs), _C128)
+    px = _dev(dpsi, "dpsi", _rows(ctx, nrhs), _C128)
+    iters = np.zeros(nk * int(nrhs), dtype=np.int32)
+    st = _lib.pw_dfpt_cg(ctx, int(prec), int(nocc), pu, pe, pa, int(nrhs), pr, px, float(thr), int(max_iter),
+                         iters.ctypes.data_as(_pi))
     _check(ctx, st, allow_noconv=True)
     return st, iters
 
 
 def pw_dfpt_rhs(ctx_kq, ctx_k, nocc: int, dv_r, psi_k, psi_occ_kq, rhs):
-    """dv_r: host complex (N1, N2, N3); device arrays as torch tensors or pointers."""
-    dv = np.ascontiguousarray(dv_r, dtype=np.complex128)
-    return _check(ctx_kq, _lib.pw_dfpt_rhs(ctx_kq, ctx_k, int(nocc), dv.ctypes.data, _ptr(psi_k), _ptr(psi_occ_kq),
-                                           _ptr(rhs)))
+    """dv_r: host complex (N1, N2, N3); psi_k: device complex128 (nk, nocc,
+    npwx_k); psi_occ_kq, rhs: device complex128 (nk, nocc, npwx_kq)."""
+    dv = _host(dv_r, "dv_r", _dims(ctx_kq)["fft"], np.complex128)
+    pk = _dev(psi_k, "psi_k", _rows(ctx_k, nocc), _C128)
+    pq = _dev(psi_occ_kq, "psi_occ_kq", _rows(ctx_kq, nocc), _C128)
+    pr = _dev(rhs, "rhs", _rows(ctx_kq, nocc), _C128)
+    return _check(ctx_kq, _lib.pw_dfpt_rhs(ctx_kq, ctx_k, int(nocc), dv.ctypes.data, pk, pq, pr))
 
 
 def pw_drho(ctx_kq, ctx_k, nbnd: int, wk, psi_k, dpsi_kq, drho_r):
-    w, pw = _dbl(wk)
-    return _check(ctx_kq, _lib.pw_drho(ctx_kq, ctx_k, int(nbnd), pw, _ptr(psi_k), _ptr(dpsi_kq), _ptr(drho_r)))
+    """wk: host (nk); psi_k: device complex128 (nk, nbnd, npwx_k); dpsi_kq:
+    device complex128 (nk, nbnd, npwx_kq); drho_r: device complex128 (N1, N2, N3)."""
+    d = _dims(ctx_kq)
+    w, pw = _dbl(_host(wk, "wk", (d["nk"],), np.float64))
+    pk = _dev(psi_k, "psi_k", _rows(ctx_k, nbnd), _C128)
+    pq = _dev(dpsi_kq, "dpsi_kq", _rows(ctx_kq, nbnd), _C128)
+    pd = _dev(drho_r, "drho_r", d["fft"], _C128)
+    return _check(ctx_kq, _lib.pw_drho(ctx_kq, ctx_k, int(nbnd), pw, pk, pq, pd))

@@ -223,15 +223,18 @@ def prewarm(reqs):
         _vloc(r.cfg)
 
 
-def replay(reqs, server: Server, speed=1.0):
-    """Submit (arrival, Request) pairs at their arrival times; wait for all."""
+def replay(reqs, server: Server, speed=1.0, report=None):
+    """Submit (arrival, Request) pairs at their arrival times; wait for all.
+    `report(n)` is called after every 100th submission."""
     t_start = server.now()
-    for r in reqs:
+    for i, r in enumerate(reqs):
         wait = t_start + r.arrival / speed - server.now()
         if wait > 0:
             time.sleep(wait)
         r.arrival = server.now()   # the moment it reached the server
         server.submit(r)
+        if report and (i + 1) % 100 == 0:
+            report(i + 1)
     while True:
         with server.cv:
             if len(server.completed) >= len(reqs):

@@ -202,6 +202,18 @@ def make_config(cid: int) -> Config:
     raise ValueError(f"unknown config id {cid}")
 
 
+def gapped(cfg: Config, scale: float = 32.0, nocc: int = 8) -> Config:
+    """The same workload with a local potential `scale` times deeper, which
+    opens a gap above band `nocc` over the whole Brillouin zone (an insulator):
+    for the two-atom cell, scale 32 leaves about 0.3 Ha between bands 8 and 9
+    over the k and k+q lists at the paper's q, so that the DFPT systems at
+    q != 0 are positive definite on the conduction states."""
+    c = Config(cfg.name.replace("fcc2", f"fcc2x{scale:g}") + f"-nocc{nocc}", cfg.lat, cfg.ecut_ry, cfg.fft,
+               cfg.kpts, cfg.nbnd, cfg.tau, cfg.projectors, cfg.dij, cfg.seed,
+               dict(cfg.extra, vloc_scale=float(scale), nocc=nocc, nrhs=nocc), cfg.qij)
+    return c
+
+
 def subset(cfg: Config, ks) -> Config:
     """Same crystal and cutoff on a subset of the k-list (indices `ks`)."""
     ks = np.asarray(ks, dtype=np.int64)
@@ -249,7 +261,8 @@ def vloc_grid(cfg: Config) -> np.ndarray:
     reciprocal lattice vectors with |G|^2 <= 4 ecut (the density cutoff) and
     placed at each atom with the structure factor exp(-i G.tau)."""
     m, g = _lattice_vectors_in_sphere(cfg.lat, 4.0 * cfg.ecut_ry)
-    vg = -3.0 * np.exp(-0.5 * np.einsum("ij,ij->i", g, g)) / cfg.omega
+    depth = 3.0 * float(cfg.extra.get("vloc_scale", 1.0))
+    vg = -depth * np.exp(-0.5 * np.einsum("ij,ij->i", g, g)) / cfg.omega
     out = np.zeros(cfg.fft)
     inv_lat = np.linalg.inv(cfg.lat)
     for t in cfg.tau:

@@ -137,6 +137,38 @@ def test_every_variant_and_workgroup_size(cid):
     assert ran >= 6
 
 
+@pytest.mark.parametrize("ecut,n", [(25.0, 18), (30.0, 20), (30.0, 32)])
+def test_other_meshes_every_variant(ecut, n):
+    # the 18^3, 20^3 and 32^3 kernels (the first two are what the 2,3,5-smooth
+    # rule gives for ecut 25 and 30 Ry, and they use the 18- and 20-point
+    # prime-factor transforms; 32^3 is a mesh larger than the rule asks for):
+    # every (variant, workgroup size) the library builds, both precisions
+    from paper_2412_01695_amd import mkpw
+    c2 = synth.make_config(2)
+    ks = np.arange(0, c2.nk, c2.nk // 10)
+    cfg = synth.Config(f"fcc1-ecut{ecut:g}-fft{n}", c2.lat, ecut, (n, n, n), c2.kpts[ks].copy(), 12, c2.tau,
+                       c2.projectors, c2.dij, c2.seed)
+    if n < 32:
+        assert synth.fft_rule(cfg.lat, ecut) == (n, n, n)
+    torch, s = _system(cfg)
+    psi = s.psi_guess()
+    ref = _oracle_rows(cfg, s, ham.vtilde(s.vloc), psi, range(cfg.nk))
+    ran = 0
+    for variant in (0, 1, 2, 3):
+        for threads in ((0,) if variant == 0 else (256, 512, 1024)):
+            mkpw.pw_set_option(s.ctx, "hpsi_variant", variant)
+            mkpw.pw_set_option(s.ctx, "hpsi_threads", threads)
+            for prec, tol in ((0, TOL64), (1, TOL32)):
+                try:
+                    h = _run(torch, s, psi, prec)
+                except mkpw.PwError as e:
+                    assert e.status == mkpw.PW_EINVAL and threads > 256, str(e)
+                    continue
+                print(n, variant, threads, prec, "rel err", _compare(h, ref, s, tol))
+                ran += 1
+    assert ran >= 8
+
+
 def test_free_electron_exact():
     # V = 0 and no projectors: H psi = (1/2)|k+G|^2 psi exactly
     cfg = synth.make_config(1)

@@ -15,17 +15,21 @@ from gpu_util import torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-def _reqs(n=8, seed=11):
+def _reqs(n=8, seed=11, big=False):
+    # n small requests; with `big`, one more of 600 k-points and 32 bands (the
+    # top of the stream's band range) at the highest cutoff
     from paper_2412_01695_amd import serve
     rng = np.random.default_rng(seed)
     lat = synth.fcc_lattice()
     b = synth.reciprocal_rows(lat)
     out = []
-    for i in range(n):
+    for i in range(n + (1 if big else 0)):
         nk = int(rng.integers(16, 48))
         ecut = float(rng.uniform(20.0, 45.0))
         nbnd = int(rng.integers(8, 17))
         nat = int(rng.integers(1, 3))
+        if i == n:
+            nk, ecut, nbnd = 600, 44.0, 32
         tau = np.zeros((1, 3)) if nat == 1 else np.array([[0.0, 0.0, 0.0], [0.25 * synth.A_FCC] * 3])
         k = np.random.default_rng([seed, i]).uniform(-0.5, 0.5, (nk, 3)) @ b
         cfg = synth.Config(f"t{i}", lat, ecut, synth.fft_rule(lat, ecut), k, nbnd, tau,
@@ -46,11 +50,11 @@ def _run(reqs, slots, budget=64 << 30, stagger=0.0):
 
 def test_alone_equals_mixed():
     torch_cuda()
-    alone = _reqs()
+    alone = _reqs(big=True)
     for r in alone:
         _run([r], 1)
         assert r.status == 0, r.error
-    mixed = _reqs()
+    mixed = _reqs(big=True)
     srv = _run(mixed, 4, stagger=0.01)
     assert all(r.status == 0 for r in mixed), [r.error for r in mixed]
     # overlap really happened: some request was admitted before another finished
@@ -76,3 +80,36 @@ def test_admission_by_budget():
     r = _reqs(1, seed=13)[0]
     _run([r], 2, budget=r.bytes // 2)
     assert r.status == mkpw.PW_ENOMEM
+
+
+def test_served_eigenvalues_match_the_oracle():
+    # requests on the 15^3, 18^3, 20^3 and 24^3 meshes the stream's cutoffs
+    # give, solved together: sampled k-points against the oracle's dense
+    # eigenvalues (mixed precision refined to 1e-6 Ry)
+    torch_cuda()
+    from oracle import hamiltonian as ham
+    from paper_2412_01695_amd import serve
+    lat = synth.fcc_lattice()
+    b = synth.reciprocal_rows(lat)
+    reqs = []
+    for i, (ecut, nat) in enumerate(((20.0, 1), (25.0, 2), (30.0, 1), (40.0, 2))):
+        tau = np.zeros((1, 3)) if nat == 1 else np.array([[0.0, 0.0, 0.0], [0.25 * synth.A_FCC] * 3])
+        k = np.random.default_rng([21, i]).uniform(-0.5, 0.5, (24, 3)) @ b
+        cfg = synth.Config(f"o{i}", lat, ecut, synth.fft_rule(lat, ecut), k, 10, tau,
+                           synth._sp_projectors(list(range(nat)), [1.0]), synth._d_one_channel(nat), 6000 + i)
+        reqs.append(serve.Request(i, 0.0, cfg, tol_ry=1e-6))
+    assert sorted({r.cfg.fft[0] for r in reqs}) == [15, 18, 20, 24]
+    _run(reqs, 4)
+
+    def bfn(c, ik, m):
+        return synth.beta_values(c, synth.q_vectors(c, ik, m))
+
+    for r in reqs:
+        assert r.status == 0, r.error
+        vt = ham.vtilde(serve._vloc(r.cfg))
+        worst = 0.0
+        for ik in (0, 11, 23):
+            ref = np.linalg.eigvalsh(ham.KPoint(r.cfg, ik, vt, bfn).h)[:r.cfg.nbnd]
+            worst = max(worst, float(np.max(np.abs(r.eig[ik] - ref))))
+        print(r.cfg.name, "FFT", r.cfg.fft[0], "max |eig err| Ha", worst)
+        assert worst < 0.5e-6

@@ -99,6 +99,52 @@ def test_davidson_mixed_refined(cid):
     assert err < TOL_MIXED_HA
 
 
+def test_davidson_mixed_before_and_after_refinement():
+    # the complex64 phase alone stops near what an FP32 H application resolves;
+    # the FP64 refinement brings every eigenvalue within 1e-6 Ry of the oracle
+    from paper_2412_01695_amd import mkpw
+    cfg0 = synth.make_config(4)
+    cfg = synth.subset(cfg0, np.arange(0, cfg0.nk, 96))
+    torch, s = _system(cfg)
+    ref = _oracle_eigs(cfg, s, range(cfg.nk), cfg.nbnd)
+    errs = {}
+    for refine in (0, 1):
+        mkpw.pw_set_option(s.ctx, "mixed_refine", refine)
+        st, eig, iters, conv, psi = _davidson(torch, s, 1, 1e-6)
+        assert st == 0 and conv.all()
+        errs[refine] = max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref)
+        print("refine", refine, "max |eig err| Ha", errs[refine], "iters", iters.min(), iters.max(),
+              "H k-bands", mkpw.pw_get_option(s.ctx, "last_hpsi_kbands"))
+    assert errs[1] < TOL_MIXED_HA
+    assert errs[0] < 1e-4
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_davidson_graph_replay_equals_eager(prec):
+    # an iteration captured as a HIP graph and replayed gives the same solve,
+    # bit for bit, as launching its kernels one by one; the two alternate on one
+    # context, with eager work and synchronisations between the replayed solves
+    from paper_2412_01695_amd import mkpw
+    cfg = synth.subset(synth.make_config(2), np.arange(0, 512, 16))
+    torch, s = _system(cfg)
+    outs = []
+    for graph in (0, 1, 0, 1, 1):
+        mkpw.pw_set_option(s.ctx, "solver_graph", graph)
+        st, eig, iters, conv, psi = _davidson(torch, s, prec, 1e-10 if prec == 0 else 1e-6)
+        assert st == 0 and conv.all()
+        replays = mkpw.pw_get_option(s.ctx, "last_graph_replays")
+        assert (replays > 0) == bool(graph)
+        outs.append((eig, iters, psi.cpu().numpy(), mkpw.pw_get_option(s.ctx, "last_hpsi_kbands")))
+        print("graph", graph, "replays", replays, "iterations", mkpw.pw_get_option(s.ctx, "last_iterations"),
+              "H k-bands", outs[-1][3])
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert np.array_equal(o[1], outs[0][1])
+        assert np.array_equal(o[2], outs[0][2])
+        assert o[3] == outs[0][3]
+    assert outs[0][3] >= cfg.nk * cfg.nbnd * (2 if prec else 1)
+
+
 def test_davidson_c2_full_batch_sampled():
     cfg = synth.make_config(2)
     torch, s = _system(cfg)
@@ -259,3 +305,54 @@ def test_cg_noconv():
     u, rhs, eps, alpha, _ = _dfpt_case(cfg, s, 5, 5)
     st, iters, x = _run_cg(torch, s, 0, u, rhs, eps, alpha, max_iter=2)
     assert st == mkpw.PW_ENOCONV
+
+
+def test_cg_iterates_follow_the_oracle_recurrence():
+    # three FP64 steps of the library's CG equal three steps of the oracle's
+    # Sec. 2.4 recurrence with its preconditioner M = max(1, (|k+G|^2/2)/T_nu):
+    # a different M (or step order) gives a different third iterate
+    cfg = synth.make_config(1)
+    torch, s = _system(cfg)
+    nocc = 5
+    u, rhs, eps, alpha, _ = _dfpt_case(cfg, s, nocc, nocc)
+    st, iters, x = _run_cg(torch, s, 0, u, rhs, eps, alpha, max_iter=3)
+    vt = ham.vtilde(s.vloc)
+    worst = 0.0
+    for ik in range(cfg.nk):
+        kp = ham.KPoint(cfg, ik, vt, beta_fn)
+        perm = miller_map(s.miller[ik], kp.miller)
+        n = s.npw[ik]
+        uo = np.zeros((kp.npw, nocc), complex)
+        uo[perm, :] = u[ik, :, :n].T
+        for nu in range(nocc):
+            a = solvers.dfpt_matrix(kp.h, uo, eps[ik, nu], alpha[ik])
+            bo = np.zeros(kp.npw, complex)
+            bo[perm] = rhs[ik, nu, :n]
+            m = solvers.dfpt_precond(kp.kin, uo[:, nu])
+            x3, it3, _ = solvers.pcg(lambda y: a @ y, lambda y: y / m, bo, np.zeros_like(bo), thr=1e-24, max_iter=3)
+            assert it3 == 3
+            worst = max(worst, np.linalg.norm(x[ik, nu, :n] - x3[perm]) / np.linalg.norm(x3))
+    print("CG third iterate vs oracle: worst rel diff", worst)
+    assert worst < 1e-10
+
+
+def test_cg_graph_replay_equals_eager():
+    # the CG's replayed iteration gives the same solutions and iteration counts
+    # as its kernels launched one by one, in both precisions
+    from paper_2412_01695_amd import mkpw
+    cfg = synth.make_config(1)
+    torch, s = _system(cfg)
+    nocc = 5
+    u, rhs, eps, alpha, _ = _dfpt_case(cfg, s, nocc, nocc)
+    for prec in (0, 1):
+        outs = []
+        for graph in (0, 1, 0, 1):
+            mkpw.pw_set_option(s.ctx, "solver_graph", graph)
+            st, iters, x = _run_cg(torch, s, prec, u, rhs, eps, alpha)
+            assert st == 0
+            assert (mkpw.pw_get_option(s.ctx, "last_graph_replays") > 0) == bool(graph)
+            outs.append((iters, x, mkpw.pw_get_option(s.ctx, "last_hpsi_kbands")))
+        for o in outs[1:]:
+            assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1]) and o[2] == outs[0][2]
+        # H applications: one per system for each restart, then one per active system per update
+        assert outs[0][2] >= cfg.nk * nocc + int(outs[0][0].sum())

@@ -180,3 +180,56 @@ def test_single_hip_runtime_whatever_the_import_order():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+class _FakeDev:
+    """Stands in for a device tensor in the binding's argument checks (its
+    pointer is never used: the host-only context refuses device work)."""
+
+    def __init__(self, shape, dtype, contiguous=True, device="cuda"):
+        self.shape, self.dtype, self._c = tuple(shape), "torch." + dtype, contiguous
+        self.device = type("D", (), {"type": device})()
+
+    def data_ptr(self):
+        return 0
+
+    def is_contiguous(self):
+        return self._c
+
+
+def test_binding_checks_device_arrays_against_the_context(mk):
+    cfg = synth.make_config(1)
+    ctx = _host_ctx(mk, cfg)
+    try:
+        npw, npwx = mk.pw_set_kpoints(ctx, cfg.kpts)
+        assert mk.pw_get_option(ctx, "nk") == cfg.nk and mk.pw_get_option(ctx, "npwx") == npwx
+        assert [mk.pw_get_option(ctx, f"fft{i}") for i in (1, 2, 3)] == list(cfg.fft)
+        good = (cfg.nk, 8, npwx)
+        bad_cases = [
+            ((cfg.nk - 1, 8, npwx), "complex128", True, "cuda"),   # too few k-points
+            ((cfg.nk, 8, npwx - 64), "complex128", True, "cuda"),  # short rows
+            (good, "complex64", True, "cuda"),                     # complex64 on the FP64 path
+            (good, "complex128", False, "cuda"),                   # a strided view
+            (good, "complex128", True, "cpu"),                     # host memory
+        ]
+        for shape, dt, contig, dev in bad_cases:
+            with pytest.raises(ValueError):
+                mk.pw_h_psi(ctx, mk.PW_FP64, 8, _FakeDev(shape, dt, contig, dev), _FakeDev(good, "complex128"))
+        with pytest.raises(ValueError):  # complex128 on the mixed path
+            mk.pw_h_psi(ctx, mk.PW_MIXED, 8, _FakeDev(good, "complex128"), _FakeDev(good, "complex128"))
+        with pytest.raises(ValueError):  # nk that is not the context's
+            mk.pw_davidson(ctx, mk.PW_FP64, 8, _FakeDev(good, "complex128"), cfg.nk + 1, 1e-10, 10)
+        with pytest.raises(ValueError):  # eps with the wrong number of systems
+            mk.pw_dfpt_cg(ctx, mk.PW_FP64, 8, _FakeDev(good, "complex128"), np.zeros((cfg.nk, 7)), np.ones(cfg.nk),
+                          8, _FakeDev(good, "complex128"), _FakeDev(good, "complex128"), 1e-20, 10)
+        with pytest.raises(ValueError):  # projector rows of the wrong length
+            mk.pw_set_projectors(ctx, np.zeros((cfg.nk, 4, npwx - 1), complex), np.eye(4))
+        with pytest.raises(ValueError):  # Miller count that is not the k-point's
+            mk.pw_get_miller(ctx, 0, int(npw[0]) - 1)
+        # arrays that pass the checks reach the library, which refuses device work here
+        for prec, dt in ((mk.PW_FP64, "complex128"), (mk.PW_MIXED, "complex64")):
+            with pytest.raises(mk.PwError) as e:
+                mk.pw_h_psi(ctx, prec, 8, _FakeDev(good, dt), _FakeDev(good, dt))
+            assert e.value.status == mk.PW_ESTATE
+    finally:
+        mk.pw_destroy(ctx)

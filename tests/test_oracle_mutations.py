@@ -139,3 +139,28 @@ def test_drho_without_the_factor_four_is_caught(monkeypatch):
 def _c1q():
     cfg = synth.make_config(1)
     return cfg, synth.shifted(cfg, synth.q_paper())
+
+
+def test_precond_full_kinetic_in_numerator_is_caught(monkeypatch):
+    # |k+G|^2 where the Sec. 2.4 preconditioner has (1/2)|k+G|^2
+    def bad(kin, u):
+        t = float(np.sum(kin * np.abs(u) ** 2))
+        return np.maximum(1.0, 2.0 * kin / t)
+    monkeypatch.setattr(solvers, "dfpt_precond", bad)
+    assert _fails(tsol.test_dfpt_precond_single_plane_wave_closed_form, tsol_c1k())
+
+
+def test_precond_unsquared_weights_are_caught(monkeypatch):
+    # T_nu weighted by |u| instead of |u|^2
+    def bad(kin, u):
+        t = float(np.sum(kin * np.abs(u)))
+        return np.maximum(1.0, kin / t)
+    monkeypatch.setattr(solvers, "dfpt_precond", bad)
+    assert not _fails(tsol.test_dfpt_precond_single_plane_wave_closed_form, tsol_c1k())  # |u| = 1 there
+    assert _fails(tsol.test_dfpt_precond_two_plane_waves_closed_form, tsol_c1k())
+
+
+def tsol_c1k():
+    cfg = synth.make_config(1)
+    vt = ham.vtilde(synth.vloc_grid(cfg))
+    return cfg, None, [ham.KPoint(cfg, ik, vt, tsol.beta_fn) for ik in range(cfg.nk)]

@@ -97,3 +97,35 @@ def test_pcg_on_a_small_spd_system():
     # one step from the exact answer stops immediately
     x2, it2, _ = solvers.pcg(lambda y: a @ y, lambda y: y, b, x_true, thr=1e-20)
     assert it2 == 0
+
+
+def test_dfpt_precond_single_plane_wave_closed_form(c1k):
+    # u = one plane wave G0 (any phase): T_nu = |k+G0|^2 / 2, so the Sec. 2.4
+    # preconditioner is M_GG = max(1, |k+G|^2 / |k+G0|^2), a ratio of squared
+    # wavevectors that no factor 1/2 survives in
+    cfg, _, kps = c1k
+    for kp in kps[1:]:
+        q2 = np.sum(synth.q_vectors(cfg, kp.ik, kp.miller) ** 2, axis=1)
+        for j in (0, kp.npw // 3, kp.npw - 1):
+            if q2[j] == 0.0:
+                continue
+            u = np.zeros(kp.npw, complex)
+            u[j] = np.exp(0.7j)
+            m = solvers.dfpt_precond(kp.kin, u)
+            np.testing.assert_allclose(m, np.maximum(1.0, q2 / q2[j]), rtol=1e-14)
+
+
+def test_dfpt_precond_two_plane_waves_closed_form(c1k):
+    # |u(Ga)|^2 = 1/4, |u(Gb)|^2 = 3/4: T_nu = (|k+Ga|^2 + 3 |k+Gb|^2) / 8, and
+    # every G with |k+G|^2 / 2 <= T_nu gets M_GG = 1
+    cfg, _, kps = c1k
+    kp = kps[2]
+    q2 = np.sum(synth.q_vectors(cfg, kp.ik, kp.miller) ** 2, axis=1)
+    a, b = 5, kp.npw - 7
+    u = np.zeros(kp.npw, complex)
+    u[a] = 0.5 * np.exp(-0.3j)
+    u[b] = np.sqrt(0.75) * 1j
+    t = (q2[a] + 3.0 * q2[b]) / 8.0
+    m = solvers.dfpt_precond(kp.kin, u)
+    np.testing.assert_allclose(m, np.maximum(1.0, 0.5 * q2 / t), rtol=1e-14)
+    assert np.all(m[0.5 * q2 <= t] == 1.0) and np.all(m[0.5 * q2 > t * (1 + 1e-12)] > 1.0)
