@@ -163,6 +163,18 @@ pw_status pw_init_guess(pw_ctx* ctx, int nbnd, uint64_t seed, void* psi);
  * complex64 for PW_MIXED; they must not overlap. */
 pw_status pw_h_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* hpsi);
 
+/* pw_h_psi for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same H|psi>, arguments and result as pw_h_psi, but the call allocates
+ * nothing, times nothing and synchronises nothing.  The potential permuted
+ * for the kernel is staged in a fixed array of the library (36^3 doubles,
+ * 373 248 bytes, one per GPU, held until the process ends; PW_EINVAL for a
+ * mesh that needs more), rebuilt on every call.  The launch shape is the one
+ * pw_h_psi has tuned for this mesh and batch size if it has, else a fixed
+ * default (no tuning).  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (different streams or threads) race. */
+pw_status pw_h_psi_noalloc(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* hpsi);
+
 /* Spsi = S psi for every k-point and band at once (Sec. 2.2 overlap
  * operator, Eqs. lambdah, delta_eq, finals): psi + sum_p delta_p beta_p with
  * delta_p = sum_q q_pq <beta_q|psi>; a copy of psi when no overlap is set.

@@ -246,6 +246,12 @@ pw_status pw_create(pw_ctx** out, int hip_device, void* hip_stream) {
       }
       c->own_stream = true;
     }
+    // this device's copy of the staging array of pw_h_psi_noalloc
+    if (mkpw::hpsi_scratch_init(c) != PW_OK) {
+      if (c->own_stream) (void)hipStreamDestroy(c->stream);
+      delete c;
+      return PW_EDEVICE;
+    }
   }
   *out = c;
   return PW_OK;

@@ -555,8 +555,12 @@ const void* hpsi_kernel_ptr(const HpsiShape& sh) {
   return nullptr;
 }
 
+// vscratch: caller-provided device memory of at least N^3 sizeof(T) bytes for
+// the permuted potential, rebuilt on every launch (nothing is allocated);
+// null: the context's own copy, built once per slab width.
 template <class T, int N, int WC>
-pw_status launch_shape(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st, HpsiShape sh) {
+pw_status launch_shape(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st, HpsiShape sh,
+                       void* vscratch = nullptr) {
   KTables t = c->tables();
   const int l3c = sh.l3c;
   const int nproj_k = c->have_proj ? c->nproj : 0;
@@ -571,17 +575,23 @@ pw_status launch_shape(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi
   if (ntask <= 0) return PW_OK;
   if (ntask > (1L << 30)) return set_err(c, PW_EINVAL, "too many (k, band) rows in one call");
   const bool fp64 = sizeof(T) == 8;
-  // permuted potential for this slab width (rebuilt when the width changes)
-  int& have = fp64 ? c->vperm_l3c64 : c->vperm_l3c32;
-  void*& vp = fp64 ? c->d_vperm64 : c->d_vperm32;
-  if (have != l3c || !vp) {
-    if (!vp) {
-      pw_status s = dev_alloc(c, (size_t)N * N * N * sizeof(T), &vp);
-      if (s != PW_OK) return s;
+  const T* v = (const T*)(fp64 ? (const void*)c->d_v64 : (const void*)c->d_v32);
+  void* vp = vscratch;
+  if (vscratch) {
+    hipLaunchKernelGGL(permute_v_kernel<T>, dim3(64), dim3(256), 0, st, v, (T*)vscratch, N, l3c);
+  } else {
+    // permuted potential for this slab width (rebuilt when the width changes)
+    int& have = fp64 ? c->vperm_l3c64 : c->vperm_l3c32;
+    void*& own = fp64 ? c->d_vperm64 : c->d_vperm32;
+    if (have != l3c || !own) {
+      if (!own) {
+        pw_status s = dev_alloc(c, (size_t)N * N * N * sizeof(T), &own);
+        if (s != PW_OK) return s;
+      }
+      hipLaunchKernelGGL(permute_v_kernel<T>, dim3(64), dim3(256), 0, st, v, (T*)own, N, l3c);
+      have = l3c;
     }
-    const T* v = (const T*)(fp64 ? (const void*)c->d_v64 : (const void*)c->d_v32);
-    hipLaunchKernelGGL(permute_v_kernel<T>, dim3(64), dim3(256), 0, st, v, (T*)vp, N, l3c);
-    have = l3c;
+    vp = own;
   }
   int per_xcd = (int)((ntask + 7) / 8);
   int nproj = c->have_proj ? c->nproj : 0;
@@ -654,7 +664,7 @@ std::vector<HpsiShape> hpsi_candidates(const KTables& t, int nproj) {
 }
 
 template <class T, int N, int WC>
-pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st) {
+pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st, void* vscratch) {
   KTables t = c->tables();
   const int nproj = c->have_proj ? c->nproj : 0;
   if (c->hpsi_variant != 0 || c->hpsi_slab != 0 || c->hpsi_threads != 0) {  // explicit shape
@@ -671,7 +681,7 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
       while (sh.l3c > 1 && hpsi_lds<T, N, WC>(t, sh.l3c, nproj, sh.threads) > kLdsPerCu) --sh.l3c;
     if (hpsi_lds<T, N, WC>(t, sh.l3c, nproj, sh.threads) > kLdsPerCu)
       return set_err(c, PW_EINVAL, "requested H|psi> slab does not fit in LDS");
-    return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh);
+    return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh, vscratch);
   }
   // autotune once per (precision, mesh, window capacity, row-count bucket);
   // launches of fewer rows than kTuneMinRows are not worth timing and take the
@@ -695,17 +705,19 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
     }
     if (it != g_hpsi_tuned.end()) {
       HpsiShape sh = it->second;
-      if (fits(sh)) return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh);
+      if (fits(sh)) return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh, vscratch);
     }
   }
-  if ((long)t.nk * sel.nvec < kTuneMinRows) {
+  // small launches, and launches that may not allocate (the tuning times
+  // candidates with events and builds their potentials), take a fixed shape
+  if ((long)t.nk * sel.nvec < kTuneMinRows || vscratch) {
     HpsiShape sh;
     sh.variant = (N % 2 == 0 && N >= 30) ? 2 : 1;
     sh.threads = sh.variant == 2 ? 512 : 256;
     sh.l3c = std::min(N, std::max(1, sh.threads / ((sh.variant == 2 ? 2 : 1) * N)));
     while (sh.l3c > 1 && hpsi_lds<T, N, WC>(t, sh.l3c, nproj, sh.threads) > kLdsPerCu / 2) --sh.l3c;
     if (!fits(sh)) return set_err(c, PW_EINVAL, "H|psi> working set does not fit in LDS for this mesh");
-    return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh);
+    return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh, vscratch);
   }
   auto cands = hpsi_candidates<T, N, WC>(t, nproj);
   if (cands.empty()) return set_err(c, PW_EINVAL, "H|psi> working set does not fit in LDS for this mesh");
@@ -777,29 +789,30 @@ constexpr int wc_next() {
 }
 
 template <class T, int N, int WC>
-pw_status launch_ladder(pw_ctx* c, int w, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st) {
+pw_status launch_ladder(pw_ctx* c, int w, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st,
+                        void* vscratch) {
   if constexpr (WC >= N) {
-    return launch_one<T, N, N>(c, sel, psi, hpsi, st);
+    return launch_one<T, N, N>(c, sel, psi, hpsi, st, vscratch);
   } else {
-    if (w <= WC) return launch_one<T, N, WC>(c, sel, psi, hpsi, st);
-    return launch_ladder<T, N, wc_next<N, WC>()>(c, w, sel, psi, hpsi, st);
+    if (w <= WC) return launch_one<T, N, WC>(c, sel, psi, hpsi, st, vscratch);
+    return launch_ladder<T, N, wc_next<N, WC>()>(c, w, sel, psi, hpsi, st, vscratch);
   }
 }
 
 // H|psi> on an N^3 mesh
 template <class T, int N>
-pw_status launch_n(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st) {
+pw_status launch_n(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st, void* vscratch) {
   const int w = std::max(c->wx, std::max(c->wy, c->wz));
-  return launch_ladder<T, N, wc_first<N>()>(c, w, sel, psi, hpsi, st);
+  return launch_ladder<T, N, wc_first<N>()>(c, w, sel, psi, hpsi, st, vscratch);
 }
 
 // one translation unit per mesh size instantiates both precisions; the
 // dispatcher only declares them
-#define MKPW_HPSI_INSTANTIATE(N)                                                                    \
-  template pw_status launch_n<double, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t); \
-  template pw_status launch_n<float, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t);
-#define MKPW_HPSI_EXTERN(N)                                                                                \
-  extern template pw_status launch_n<double, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t); \
-  extern template pw_status launch_n<float, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t);
+#define MKPW_HPSI_INSTANTIATE(N)                                                                            \
+  template pw_status launch_n<double, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t, void*); \
+  template pw_status launch_n<float, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t, void*);
+#define MKPW_HPSI_EXTERN(N)                                                                                        \
+  extern template pw_status launch_n<double, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t, void*); \
+  extern template pw_status launch_n<float, N>(pw_ctx*, const VecSel&, const void*, void*, hipStream_t, void*);
 
 }  // namespace mkpw

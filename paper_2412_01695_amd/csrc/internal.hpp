@@ -175,8 +175,11 @@ pw_status host_pinned(pw_ctx* c, size_t bytes, void** out);
 
 // H|psi> over the selected vectors (kernels in hpsi.hip). psi/hpsi are
 // complex double (prec = PW_FP64) or complex float (PW_MIXED).
+// vscratch: see launch_shape (hpsi_kernel.hpp); null for the context's own
+// permuted potential.
 pw_status launch_hpsi(pw_ctx* c, pw_prec prec, const VecSel& sel, const void* psi, void* hpsi,
-                      hipStream_t stream);
+                      hipStream_t stream, void* vscratch = nullptr);
+pw_status hpsi_scratch_init(pw_ctx* c);
 bool hpsi_supported(int n1, int n2, int n3);
 
 // S|psi> = psi + sum_pq beta_p q_pq <beta_q|psi> over the selected vectors

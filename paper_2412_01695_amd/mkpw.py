@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EDEVICE", 
 
 EXPORTS = ["pw_create", "pw_destroy", "pw_last_error", "pw_set_option", "pw_get_option", "pw_set_lattice", "pw_set_cutoff",
            "pw_set_kpoints", "pw_get_miller", "pw_set_vloc", "pw_set_projectors", "pw_set_qij", "pw_init_guess",
-           "pw_h_psi", "pw_s_psi", "pw_davidson", "pw_dfpt_cg", "pw_dfpt_rhs", "pw_drho"]
+           "pw_h_psi", "pw_h_psi_noalloc", "pw_s_psi", "pw_davidson", "pw_dfpt_cg", "pw_dfpt_rhs", "pw_drho"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2412_01695_amd.build`")
@@ -60,6 +60,7 @@ _sig = {
     "pw_set_qij": (_i, [_vp, _vp]),
     "pw_init_guess": (_i, [_vp, _i, C.c_uint64, _vp]),
     "pw_h_psi": (_i, [_vp, _i, _i, _vp, _vp]),
+    "pw_h_psi_noalloc": (_i, [_vp, _i, _i, _vp, _vp]),
     "pw_s_psi": (_i, [_vp, _i, _i, _vp, _vp]),
     "pw_davidson": (_i, [_vp, _i, _i, _vp, _pd, _d, _i, _pi, _pi]),
     "pw_dfpt_cg": (_i, [_vp, _i, _i, _vp, _pd, _pd, _i, _vp, _vp, _d, _i, _pi]),
@@ -280,6 +281,13 @@ def pw_h_psi(ctx, prec: int, nbnd: int, psi, hpsi):
     shape, dt = _rows(ctx, nbnd), _wf(prec)
     p, h = _dev(psi, "psi", shape, dt), _dev(hpsi, "hpsi", shape, dt)
     return _check(ctx, _lib.pw_h_psi(ctx, int(prec), int(nbnd), p, h))
+
+
+def pw_h_psi_noalloc(ctx, prec: int, nbnd: int, psi, hpsi):
+    """pw_h_psi without any device allocation (fixed staging array per GPU)."""
+    shape, dt = _rows(ctx, nbnd), _wf(prec)
+    p, h = _dev(psi, "psi", shape, dt), _dev(hpsi, "hpsi", shape, dt)
+    return _check(ctx, _lib.pw_h_psi_noalloc(ctx, int(prec), int(nbnd), p, h))
 
 
 def pw_s_psi(ctx, prec: int, nbnd: int, psi, spsi):
