@@ -74,8 +74,10 @@ const char* pw_last_error(const pw_ctx* ctx);
  * (maximum Davidson basis in units of nbnd, default 4, Sec. 5.3), "trace"
  * (nonzero: synchronise and check after every launch), "hpsi_variant"
  * (0 = autotuned on first use, 1 = one work-item per FFT line, 2 = two lanes
- * per line, 3 = two lanes per x line and one per y and z line; 2 and 3 on even
- * meshes only), "hpsi_slab" (0 = autotuned, else the number of z planes
+ * per line, 3 = two lanes per x line and one per y and z line, 4 = one
+ * work-item per line with each x line evaluated as one convolution over the
+ * window, 5 = as 4 with two lanes per y and z line; 2, 3 and 5 on even meshes
+ * only; 4 and 5 where the window is narrower than the mesh), "hpsi_slab" (0 = autotuned, else the number of z planes
  * transformed together) and "hpsi_threads" (0 = autotuned, else 256, 512 or
  * 1024 work-items per workgroup where the kernel fits in the registers
  * that leaves; PW_EINVAL otherwise).  Any nonzero shape option fixes the
@@ -166,10 +168,11 @@ pw_status pw_h_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* h
 /* pw_h_psi for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation):
  * the same H|psi>, arguments and result as pw_h_psi, but the call allocates
- * nothing, times nothing and synchronises nothing.  The potential permuted
- * for the kernel is staged in a fixed array of the library (36^3 doubles,
- * 373 248 bytes, one per GPU, held until the process ends; PW_EINVAL for a
- * mesh that needs more), rebuilt on every call.  The launch shape is the one
+ * nothing, times nothing and synchronises nothing.  What the kernel reads of
+ * the potential (V permuted for its slab width, or the taps of its x-line
+ * convolutions) is staged in a fixed array of the library (808 704 bytes, one
+ * per GPU, held until the process ends; PW_EINVAL for a mesh that needs
+ * more), rebuilt on every call.  The launch shape is the one
  * pw_h_psi has tuned for this mesh and batch size if it has, else a fixed
  * default (no tuning).  Every call on one GPU shares that GPU's array:
  * calls that overlap on one GPU (different streams or threads) race. */

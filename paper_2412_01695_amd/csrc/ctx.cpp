@@ -171,11 +171,12 @@ void free_kdata(pw_ctx* c) {
 void free_all(pw_ctx* c) {
   free_kdata(c);
   for (void** p : {(void**)&c->d_v64, (void**)&c->d_v32, (void**)&c->d_dij64, (void**)&c->d_dij32,
-                   (void**)&c->d_vperm64, (void**)&c->d_vperm32}) {
+                   (void**)&c->d_vperm64, (void**)&c->d_vperm32, (void**)&c->d_xtaps64, (void**)&c->d_xtaps32}) {
     dev_free(c, *p);
     *p = nullptr;
   }
   c->vperm_l3c64 = c->vperm_l3c32 = 0;
+  c->xtaps_wc64 = c->xtaps_wc32 = 0;
   c->have_v = false;
 }
 
@@ -287,7 +288,7 @@ pw_status pw_set_option(pw_ctx* c, const char* key, int64_t value) {
   } else if (k == "trace") {
     c->trace = value;
   } else if (k == "hpsi_variant") {
-    if (value < 0 || value > 3) return set_err(c, PW_EINVAL, "hpsi_variant must be 0, 1, 2 or 3");
+    if (value < 0 || value > 5) return set_err(c, PW_EINVAL, "hpsi_variant must be in [0, 5]");
     c->hpsi_variant = value;
   } else if (k == "hpsi_slab") {
     if (value < 0 || value > 512) return set_err(c, PW_EINVAL, "hpsi_slab must be in [0, 512]");
@@ -581,7 +582,8 @@ pw_status pw_set_vloc(pw_ctx* c, const double* v) {
   dev_free(c, c->d_v32);
   c->d_v64 = nullptr;
   c->d_v32 = nullptr;
-  c->vperm_l3c64 = c->vperm_l3c32 = 0;  // permuted copies are rebuilt from the new potential
+  c->vperm_l3c64 = c->vperm_l3c32 = 0;  // permuted copies and x taps are rebuilt from the new potential
+  c->xtaps_wc64 = c->xtaps_wc32 = 0;
   c->have_v = false;
   pw_status s;
   if ((s = upload(c, v64.data(), nr, &c->d_v64)) != PW_OK) return s;

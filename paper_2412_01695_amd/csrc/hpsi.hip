@@ -3,6 +3,7 @@
 // hpsi_n<N>.hip) and the process-wide autotuning table.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -43,9 +44,11 @@ pw_status launch_t(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hi
 }
 
 // Staging of pw_h_psi_noalloc: the potential permuted for the kernel's slab
-// width, N^3 values of the launch's precision, for every supported mesh (the
-// largest is 36^3 in FP64).  One copy per GPU, held until the process ends.
-constexpr size_t kNoallocScratchBytes = 36u * 36u * 36u * sizeof(double);
+// width (N^3 values of the launch's precision) or the x-line convolution taps
+// (N^2 lines x at most N + 3 complex taps), for every supported mesh (the
+// largest is 36^3 in FP64: 36^2 x 39 complex doubles).  One copy per GPU,
+// held until the process ends.
+constexpr size_t kNoallocScratchBytes = 36u * 36u * 39u * 2u * sizeof(double);
 static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 // Its device address per GPU (the array's name is a host-side stand-in, not a
@@ -102,7 +105,9 @@ extern "C" pw_status pw_h_psi_noalloc(pw_ctx* c, pw_prec prec, int nbnd, const v
   if (prec != PW_FP64 && prec != PW_MIXED) return set_err(c, PW_EINVAL, "unknown precision");
   if (nbnd <= 0 || nbnd > 65535) return set_err(c, PW_EINVAL, "nbnd must be in [1, 65535]");
   if (!psi || !hpsi) return set_err(c, PW_EINVAL, "null psi or hpsi");
-  const size_t need = (size_t)c->fft[0] * c->fft[1] * c->fft[2] * (prec == PW_FP64 ? sizeof(double) : sizeof(float));
+  const size_t real = prec == PW_FP64 ? sizeof(double) : sizeof(float);
+  const size_t n = (size_t)c->fft[0];
+  const size_t need = std::max(n * n * n * real, n * n * (n + 3) * 2 * real);
   if (need > kNoallocScratchBytes)
     return set_err(c, PW_EINVAL, "pw_h_psi_noalloc: the mesh needs " + std::to_string(need) +
                                      " bytes of staging, more than its " + std::to_string(kNoallocScratchBytes));

@@ -259,10 +259,13 @@ __host__ __device__ inline HpsiLds hpsi_lds_layout(int smax, int wx, int l3c, in
 }
 
 // ZYP: z and y passes in lane pairs; XP: x pass in lane pairs (even N only).
+// XC: each x line as one convolution over the window instead (XP unused).
 // WC: compile-time capacity of the Miller window along each axis (>= the
 // actual extents wx, wy, wz); entries beyond the actual window are zero.
 // NT: work-items per workgroup (256, 512 or 1024).
-template <class T, int N, int WC, bool ZYP, bool XP, int NT>
+// vr: V/N_r permuted per slab width (Vp[slab][l1][lc][l2]); with XC the x
+// taps of V/N_r instead (xtaps_kernel).
+template <class T, int N, int WC, bool ZYP, bool XP, int NT, bool XC = false>
 __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int nproj,
                                                   const cplx<T>* __restrict__ beta,
                                                   const cplx<T>* __restrict__ dij,
@@ -271,6 +274,7 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
                                                   cplx<T>* __restrict__ hpsi, int l3c, int per_xcd,
                                                   int ntask) {
   static_assert(!(ZYP || XP) || N % 2 == 0, "lane-pair passes need an even length");
+  static_assert(!XC || WC < N, "the x convolution is for windows narrower than the mesh");
   Row<T> r;
   if (!row_of_block(t, sel, nproj, beta, psi, hpsi, per_xcd, ntask, r)) return;
   const int wx = t.wx, wy = t.wy;
@@ -425,6 +429,43 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
           [&](int j, cplx<T> v) { lds_st(yh + (ZYP ? 2 : 1) * j, v); });
     }
     __syncthreads();
+    if constexpr (XC) {
+      // x lines as convolutions: the inverse transform along x, the product
+      // with V/N_r and the forward transform along x of one line together are
+      // out(m') = sum_m X[m' - m] in(m) over the window (Eqs. xfft, fwFFT),
+      // X[d] = sum_l1 V(l1)/N_r exp(-2 pi i d l1 / N) the line's taps, read
+      // from xt[l3][d + WC - 1][l2]; a work-item owns one line, in place
+      constexpr int DW = 2 * WC - 1;
+      const cplx<T>* xt = reinterpret_cast<const cplx<T>*>(vr);
+      for (int i = tid; i < N * nl; i += NT) {
+        const int lcn = i / N, l2 = i - lcn * N;
+        lc* y = Y + lcn * wx * YS + l2;
+        const cplx<T>* tp = xt + (long)(l30 + lcn) * DW * N + l2;
+        cplx<T> in[WC], out[WC];
+        sfor<WC>([&](auto mm) {
+          constexpr int M = decltype(mm)::value;
+          in[M] = M < wx ? lds_ld(y + M * YS) : zero;
+          out[M] = zero;
+        });
+        sfor<DW>([&](auto dd) {
+          constexpr int DD = decltype(dd)::value;
+          constexpr int D = DD - (WC - 1);  // m' - m
+          const cplx<T> tap = tp[(long)DD * N];
+          sfor<WC>([&](auto mp) {
+            constexpr int MP = decltype(mp)::value;
+            constexpr int M = MP - D;
+            if constexpr (M >= 0 && M < WC) {
+              out[MP].x += tap.x * in[M].x - tap.y * in[M].y;
+              out[MP].y += tap.x * in[M].y + tap.y * in[M].x;
+            }
+          });
+        });
+        sfor<WC>([&](auto mm) {
+          constexpr int M = decltype(mm)::value;
+          if (M < wx) lds_st(y + M * YS, out[M]);
+        });
+      }
+    } else {
     // x lines: W inputs -> N points -> * V/N_r -> forward -> W outputs
     for (int i = x_slot; i < N * nl; i += kXStride) {
       const int h = lane_half(h0);
@@ -441,6 +482,7 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
           [&](int k, cplx<T> v) {
             if (k + mo < wx) lds_st(yo + k * YS, v);
           });
+    }
     }
     __syncthreads();
     // forward y: N inputs -> W outputs, back into the sticks (outputs with no
@@ -497,8 +539,38 @@ __global__ void permute_v_kernel(const T* __restrict__ v, T* __restrict__ vp, in
   }
 }
 
+// Taps of the x-line convolutions: xt[l3][d + wc - 1][l2] =
+// sum_l1 v[l1][l2][l3] exp(-2 pi i d l1 / n) for |d| < wc, from V/N_r in FP64
+// (then rounded to T).
+template <class T>
+__global__ void xtaps_kernel(const double* __restrict__ v, cplx<T>* __restrict__ xt, int n, int wc) {
+  const int dw = 2 * wc - 1;
+  const long total = (long)n * dw * n;
+  for (long o = blockIdx.x * (long)blockDim.x + threadIdx.x; o < total; o += (long)gridDim.x * blockDim.x) {
+    const int l2 = (int)(o % n);
+    const long r = o / n;
+    const int dd = (int)(r % dw), l3 = (int)(r / dw);
+    const int d = ((dd - (wc - 1)) % n + n) % n;
+    double sr = 0.0, si = 0.0;
+    int ph = 0;  // d l1 mod n
+    for (int l1 = 0; l1 < n; ++l1) {
+      double sn, cs;
+      sincospi(2.0 * ph / n, &sn, &cs);
+      const double vv = v[((long)l1 * n + l2) * n + l3];
+      sr += vv * cs;
+      si -= vv * sn;
+      ph += d;
+      if (ph >= n) ph -= n;
+    }
+    xt[o] = {(T)sr, (T)si};
+  }
+}
+
 // Shape of one launch: kernel variant (1 = one work-item per line, 2 = lane
-// pair per line, even N only), slab width in z planes, work-items per workgroup.
+// pair per line, even N only, 3 = lane pairs for the x lines only, 4 = one
+// work-item per line with each x line as a convolution, 5 = lane pairs for
+// the y and z lines with x convolutions; 4 and 5 for windows narrower than the
+// mesh), slab width in z planes, work-items per workgroup.
 struct HpsiShape {
   int variant = 1;
   int l3c = 1;
@@ -527,22 +599,31 @@ constexpr bool allow_512() {
 }
 template <class T, int N, int VARIANT>
 constexpr bool allow_1024() {
+  if constexpr (VARIANT == 4) return sizeof(T) == 4 && N <= 24;
+  if constexpr (VARIANT == 5) return true;
   return sizeof(T) == 4 ? (VARIANT != 1 || N <= 20) : VARIANT == 2;
 }
 
 template <class T, int N, int WC, int VARIANT>
 const void* kernel_for(int threads) {
   // variant 1: one work-item per line; 2: lane pairs for every line;
-  // 3: lane pairs for the x lines only (their registers set the occupancy)
-  constexpr bool ZYP = VARIANT == 2, XP = VARIANT != 1;
-  if (threads == 256) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 256>;
-  if constexpr (allow_512<T, N, VARIANT>()) {
-    if (threads == 512) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 512>;
+  // 3: lane pairs for the x lines only (their registers set the occupancy);
+  // 4: one work-item per line, x lines as convolutions; 5: lane pairs for the
+  // y and z lines, x lines as convolutions
+  constexpr bool ZYP = VARIANT == 2 || VARIANT == 5, XP = VARIANT == 2 || VARIANT == 3;
+  constexpr bool XC = VARIANT >= 4;
+  if constexpr (XC && WC >= N) {
+    return nullptr;
+  } else {
+    if (threads == 256) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 256, XC>;
+    if constexpr (allow_512<T, N, VARIANT>()) {
+      if (threads == 512) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 512, XC>;
+    }
+    if constexpr (allow_1024<T, N, VARIANT>()) {
+      if (threads == 1024) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 1024, XC>;
+    }
+    return nullptr;
   }
-  if constexpr (allow_1024<T, N, VARIANT>()) {
-    if (threads == 1024) return (const void*)hpsi_kernel<T, N, WC, ZYP, XP, 1024>;
-  }
-  return nullptr;
 }
 
 template <class T, int N, int WC>
@@ -550,8 +631,10 @@ const void* hpsi_kernel_ptr(const HpsiShape& sh) {
   if constexpr (N % 2 == 0) {
     if (sh.variant == 2) return kernel_for<T, N, WC, 2>(sh.threads);
     if (sh.variant == 3) return kernel_for<T, N, WC, 3>(sh.threads);
+    if (sh.variant == 5) return kernel_for<T, N, WC, 5>(sh.threads);
   }
   if (sh.variant == 1) return kernel_for<T, N, WC, 1>(sh.threads);
+  if (sh.variant == 4) return kernel_for<T, N, WC, 4>(sh.threads);
   return nullptr;
 }
 
@@ -577,7 +660,29 @@ pw_status launch_shape(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi
   const bool fp64 = sizeof(T) == 8;
   const T* v = (const T*)(fp64 ? (const void*)c->d_v64 : (const void*)c->d_v32);
   void* vp = vscratch;
-  if (vscratch) {
+  const size_t taps_bytes = (size_t)N * N * (2 * WC - 1) * sizeof(cplx<T>);
+  if (sh.variant >= 4) {
+    // x-line taps for this window capacity (rebuilt when it changes)
+    if (vscratch) {
+      hipLaunchKernelGGL(xtaps_kernel<T>, dim3(256), dim3(256), 0, st, c->d_v64, (cplx<T>*)vscratch, N, WC);
+    } else {
+      int& have = fp64 ? c->xtaps_wc64 : c->xtaps_wc32;
+      void*& own = fp64 ? c->d_xtaps64 : c->d_xtaps32;
+      if (have != WC || !own) {
+        if (own && have != WC) {
+          dev_free(c, own);
+          own = nullptr;
+        }
+        if (!own) {
+          pw_status s = dev_alloc(c, taps_bytes, &own);
+          if (s != PW_OK) return s;
+        }
+        hipLaunchKernelGGL(xtaps_kernel<T>, dim3(256), dim3(256), 0, st, c->d_v64, (cplx<T>*)own, N, WC);
+        have = WC;
+      }
+      vp = own;
+    }
+  } else if (vscratch) {
     hipLaunchKernelGGL(permute_v_kernel<T>, dim3(64), dim3(256), 0, st, v, (T*)vscratch, N, l3c);
   } else {
     // permuted potential for this slab width (rebuilt when the width changes)
@@ -634,16 +739,20 @@ inline int wgs_by_vgpr(const void* kern, int threads) {
 // Candidate shapes: for each variant and workgroup size, the whole mesh as one
 // slab, and the widest slab that fits in the LDS share for 1, 2 or 3
 // workgroups per CU (as many as the registers allow), capped where every x
-// line already has its own work-item (or lane pair).
+// line already has its own work-item (or lane pair); and, for one workgroup
+// per CU, every slab width that splits the mesh evenly into a different
+// number of slabs (ceil(N / s) planes) and fits: the number of slabs sets how
+// many y passes run and how the x lines fill the work-items in the last round
+// of each slab, which no single width balances for every mesh.
 template <class T, int N, int WC>
 std::vector<HpsiShape> hpsi_candidates(const KTables& t, int nproj) {
   std::vector<HpsiShape> out;
-  for (int variant : {1, 2, 3}) {
-    if (variant != 1 && N % 2) continue;
+  for (int variant : {1, 2, 3, 4, 5}) {
+    if ((variant == 2 || variant == 3 || variant == 5) && N % 2) continue;
     for (int threads : {256, 512, 1024}) {
       const void* kern = hpsi_kernel_ptr<T, N, WC>({variant, 1, threads});
       if (!kern) continue;
-      const int lanes = variant != 1 ? 2 : 1;  // work-items per x line
+      const int lanes = (variant == 2 || variant == 3) ? 2 : 1;  // work-items per x line
       const int cap = std::min(N, std::max(1, threads / (lanes * N)));
       const int max_wg = std::min(3, wgs_by_vgpr(kern, threads));  // 0: spills, skipped
       // the whole mesh in one slab, and for 1..max_wg workgroups per CU the
@@ -653,6 +762,15 @@ std::vector<HpsiShape> hpsi_candidates(const KTables& t, int nproj) {
         const size_t share = kLdsPerCu / (wg ? wg : 1);
         int l3c = wg == 0 ? N : cap;
         while (l3c > 1 && hpsi_lds<T, N, WC>(t, l3c, nproj, threads) > share) --l3c;
+        if (hpsi_lds<T, N, WC>(t, l3c, nproj, threads) > kLdsPerCu) continue;
+        bool dup = false;
+        for (auto& o : out) dup = dup || (o.variant == variant && o.l3c == l3c && o.threads == threads);
+        if (!dup) out.push_back({variant, l3c, threads});
+      }
+      if (max_wg == 0) continue;
+      for (int nslab = 2; nslab <= 6; ++nslab) {
+        const int l3c = (N + nslab - 1) / nslab;
+        if (l3c * lanes * N < threads / 2) break;  // x lines would leave most work-items idle
         if (hpsi_lds<T, N, WC>(t, l3c, nproj, threads) > kLdsPerCu) continue;
         bool dup = false;
         for (auto& o : out) dup = dup || (o.variant == variant && o.l3c == l3c && o.threads == threads);
@@ -668,13 +786,14 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
   KTables t = c->tables();
   const int nproj = c->have_proj ? c->nproj : 0;
   if (c->hpsi_variant != 0 || c->hpsi_slab != 0 || c->hpsi_threads != 0) {  // explicit shape
-    if (c->hpsi_variant >= 2 && N % 2) return set_err(c, PW_EINVAL, "lane-pair variants need an even mesh");
+    if ((c->hpsi_variant == 2 || c->hpsi_variant == 3 || c->hpsi_variant == 5) && N % 2)
+      return set_err(c, PW_EINVAL, "lane-pair variants need an even mesh");
     HpsiShape sh;
     sh.variant = c->hpsi_variant ? (int)c->hpsi_variant : 1;
     sh.threads = c->hpsi_threads ? (int)c->hpsi_threads : 256;
     if (!hpsi_kernel_ptr<T, N, WC>(sh))
       return set_err(c, PW_EINVAL, "no H|psi> kernel for this variant and workgroup size on this mesh");
-    const int lanes = sh.variant != 1 ? 2 : 1;
+    const int lanes = (sh.variant == 2 || sh.variant == 3) ? 2 : 1;
     sh.l3c = c->hpsi_slab ? (int)std::min<int64_t>(c->hpsi_slab, N)
                           : std::min(N, std::max(1, sh.threads / (lanes * N)));
     if (!c->hpsi_slab)
@@ -724,8 +843,8 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
   HpsiShape sh = cands[0];
   if (cands.size() > 1) {
     // two rounds: every candidate once (one warm-up launch, which also builds
-    // its permuted V, then two timed), then the three fastest again with five
-    // timed launches each
+    // what it reads of the potential, then one timed), then the three fastest
+    // again with four timed launches each
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
       (void)hipGetLastError();
@@ -746,7 +865,7 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
     std::vector<std::pair<float, size_t>> t1;
     for (size_t i = 0; i < cands.size(); ++i) {
       float ms = 0.f;
-      if (!time_it(cands[i], 2, &ms)) break;
+      if (!time_it(cands[i], 1, &ms)) break;
       t1.push_back({ms, i});
       if (c->tune_log)
         fprintf(stderr, "hpsi tune fp%d N=%d WC=%d variant=%d threads=%d slab=%d: %.4f ms\n", (int)sizeof(T) * 8,
@@ -757,7 +876,7 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
       float best = 1e30f;
       for (size_t j = 0; j < std::min<size_t>(3, t1.size()); ++j) {
         float ms = 0.f;
-        if (!time_it(cands[t1[j].second], 5, &ms)) break;
+        if (!time_it(cands[t1[j].second], 4, &ms)) break;
         if (ms < best) {
           best = ms;
           sh = cands[t1[j].second];

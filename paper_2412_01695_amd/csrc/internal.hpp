@@ -151,6 +151,9 @@ struct pw_ctx {
   void* d_vperm64 = nullptr;  // V/N_r permuted for the kernel's slab width
   void* d_vperm32 = nullptr;
   int vperm_l3c64 = 0, vperm_l3c32 = 0;
+  void* d_xtaps64 = nullptr;  // x-line convolution taps of V/N_r for a window capacity
+  void* d_xtaps32 = nullptr;
+  int xtaps_wc64 = 0, xtaps_wc32 = 0;
   int nproj = 0;
   void* d_beta64 = nullptr;  // (nk, nproj, npwx) complex double
   void* d_beta32 = nullptr;  // complex float

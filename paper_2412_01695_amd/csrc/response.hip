@@ -18,7 +18,9 @@
 //     blocked over 4 x 4 pairs, bands staged in LDS) into bins of the Miller
 //     difference d = m_G2 - m_G1 held in LDS; the per-k bins are summed over k
 //     into the mesh (d mod N; 64 chunks of k summed in parallel, then the
-//     chunks in a fixed order) and one inverse transform of the mesh gives
+//     chunks in a fixed order; the per-k bins themselves are summed with LDS
+//     atomics, so results agree to rounding between runs, not bit for bit)
+//     and one inverse transform of the mesh gives
 //     drho(r) = sum_d F(d) exp(2 pi i d.l / N).
 // The transforms of the single mesh (dV(r) -> dV~ with 1/N_r, F -> drho(r))
 // are separable direct sums, one launch per axis.
@@ -89,8 +91,13 @@ __global__ __launch_bounds__(kVT) void dvpsi_kernel(const cd* __restrict__ dvt, 
   const int nin = npw_in[k], nout = npw_out[k];
   __shared__ cd us[kVB][kVG];
   __shared__ int ms[3][kVG];
+  // mesh index of m_G' - m_G on each axis as (m_G' mod n) + (-m_G mod n),
+  // both in [0, n), less n when the sum reaches n: no division per pair
   int p1 = 0, p2 = 0, p3 = 0;
   if (gp < nout) unpack_miller(key_out[(long)k * npwx_out + gp], p1, p2, p3);
+  p1 = wrap(p1, n1);
+  p2 = wrap(p2, n2);
+  p3 = wrap(p3, n3);
   for (int b0 = 0; b0 < nbnd; b0 += kVB) {
     double ar[kVB], ai[kVB];
 #pragma unroll
@@ -104,15 +111,19 @@ __global__ __launch_bounds__(kVT) void dvpsi_kernel(const cd* __restrict__ dvt, 
       for (int g = threadIdx.x; g < kVG; g += kVT) {
         int a = 0, b = 0, c = 0;
         if (g0 + g < nin) unpack_miller(key_in[(long)k * npwx_in + g0 + g], a, b, c);
-        ms[0][g] = a;
-        ms[1][g] = b;
-        ms[2][g] = c;
+        ms[0][g] = wrap(-a, n1);
+        ms[1][g] = wrap(-b, n2);
+        ms[2][g] = wrap(-c, n3);
       }
       __syncthreads();
       if (gp < nout) {
         const int ng = min(kVG, nin - g0);
         for (int g = 0; g < ng; ++g) {
-          const long idx = ((long)wrap(p1 - ms[0][g], n1) * n2 + wrap(p2 - ms[1][g], n2)) * n3 + wrap(p3 - ms[2][g], n3);
+          int d1 = p1 + ms[0][g], d2 = p2 + ms[1][g], d3 = p3 + ms[2][g];
+          d1 -= d1 >= n1 ? n1 : 0;
+          d2 -= d2 >= n2 ? n2 : 0;
+          d3 -= d3 >= n3 ? n3 : 0;
+          const int idx = (d1 * n2 + d2) * n3 + d3;
           const cd v = dvt[idx];
 #pragma unroll
           for (int b = 0; b < kVB; ++b) {
@@ -133,13 +144,19 @@ __global__ __launch_bounds__(kVT) void dvpsi_kernel(const cd* __restrict__ dvt, 
   }
 }
 
-constexpr int kRT = 64;  // plane waves of each sphere per pair tile
-constexpr int kRB = 16;  // bands staged per step
+constexpr int kRT = 64;    // plane waves of each sphere per pair tile
+constexpr int kRB = 16;    // bands staged per step
+constexpr int kRW = 1024;  // work-items per k-point: a 32 x 32 grid of 2 x 2 pair blocks
 
 // Per k: bins F_k(d) += 4 w_k sum_nu conj(u1(G1)) u2(G2) over the pairs with
 // d = m_G2 - m_G1 - org_k in the box [0, D1) x [0, D2) x [0, D3), for the
 // slice x0 <= d1 < x0 + nx held in LDS; the slice is written to part[k].
-__global__ __launch_bounds__(256) void drho_pairs_kernel(int nbnd, const double* __restrict__ wk,
+// The bins fill most of the LDS, so one workgroup runs per CU: it has 16
+// waves, each work-item summing a 2 x 2 block of pairs of the 64 x 64 tile
+// over the bands staged in LDS, so that enough waves hide the LDS latency.
+// The bins are summed with LDS atomics: the order of the additions into a bin
+// varies from run to run (results agree to rounding, not bit for bit).
+__global__ __launch_bounds__(kRW) void drho_pairs_kernel(int nbnd, const double* __restrict__ wk,
                                                          const int* __restrict__ npw1, const int* __restrict__ key1,
                                                          int npwx1, const cd* __restrict__ u1,
                                                          const int* __restrict__ npw2, const int* __restrict__ key2,
@@ -156,28 +173,29 @@ __global__ __launch_bounds__(256) void drho_pairs_kernel(int nbnd, const double*
   int* ma = reinterpret_cast<int*>(vs + kRB * kRT);  // [3][kRT]
   int* mb = ma + 3 * kRT;                            // [3][kRT]
   const int k = blockIdx.x;
-  for (int e = threadIdx.x; e < nbin; e += 256) bre[e] = bim[e] = 0.0;
+  for (int e = threadIdx.x; e < nbin; e += kRW) bre[e] = bim[e] = 0.0;
   const int n1 = npw1[k], n2 = npw2[k];
   const double f = 4.0 * wk[k];
   const int o1 = org[3 * k], o2 = org[3 * k + 1], o3 = org[3 * k + 2];
-  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  constexpr int kBl = 2;  // pairs per work-item along each sphere
+  const int ti = threadIdx.x >> 5, tj = threadIdx.x & 31;
   for (int i0 = 0; i0 < n1; i0 += kRT) {
     for (int j0 = 0; j0 < n2; j0 += kRT) {
-      double cr[4][4], ci[4][4];
+      double cr[kBl][kBl], ci[kBl][kBl];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < kBl; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) cr[a][c] = ci[a][c] = 0.0;
+        for (int c = 0; c < kBl; ++c) cr[a][c] = ci[a][c] = 0.0;
       for (int b0 = 0; b0 < nbnd; b0 += kRB) {
         __syncthreads();
-        for (int e = threadIdx.x; e < kRB * kRT; e += 256) {
+        for (int e = threadIdx.x; e < kRB * kRT; e += kRW) {
           const int b = e / kRT, g = e % kRT;
           const bool bok = b0 + b < nbnd;
           us[e] = (bok && i0 + g < n1) ? u1[((long)k * nbnd + b0 + b) * npwx1 + i0 + g] : cd{0.0, 0.0};
           vs[e] = (bok && j0 + g < n2) ? u2[((long)k * nbnd + b0 + b) * npwx2 + j0 + g] : cd{0.0, 0.0};
         }
         if (b0 == 0) {
-          for (int g = threadIdx.x; g < kRT; g += 256) {
+          for (int g = threadIdx.x; g < kRT; g += kRW) {
             int a = 0, b = 0, c = 0;
             if (i0 + g < n1) unpack_miller(key1[(long)k * npwx1 + i0 + g], a, b, c);
             ma[g] = a;
@@ -191,30 +209,31 @@ __global__ __launch_bounds__(256) void drho_pairs_kernel(int nbnd, const double*
           }
         }
         __syncthreads();
+#pragma unroll 4
         for (int b = 0; b < kRB; ++b) {
-          cd x[4], y[4];
+          cd x[kBl], y[kBl];
 #pragma unroll
-          for (int a = 0; a < 4; ++a) x[a] = us[b * kRT + ti * 4 + a];
+          for (int a = 0; a < kBl; ++a) x[a] = us[b * kRT + ti * kBl + a];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) y[c] = vs[b * kRT + tj * 4 + c];
+          for (int c = 0; c < kBl; ++c) y[c] = vs[b * kRT + tj * kBl + c];
 #pragma unroll
-          for (int a = 0; a < 4; ++a)
+          for (int a = 0; a < kBl; ++a)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < kBl; ++c) {
               // conj(x) * y
               cr[a][c] += x[a].x * y[c].x + x[a].y * y[c].y;
               ci[a][c] += x[a].x * y[c].y - x[a].y * y[c].x;
             }
         }
       }
-      // scatter the 4 x 4 block into the bins of this slice
+      // scatter the 2 x 2 block into the bins of this slice
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int g1 = ti * 4 + a;
+      for (int a = 0; a < kBl; ++a) {
+        const int g1 = ti * kBl + a;
         if (i0 + g1 >= n1) continue;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int g2 = tj * 4 + c;
+        for (int c = 0; c < kBl; ++c) {
+          const int g2 = tj * kBl + c;
           if (j0 + g2 >= n2) continue;
           const int d1 = mb[g2] - ma[g1] - o1 - x0;
           if (d1 < 0 || d1 >= nx) continue;
@@ -229,12 +248,12 @@ __global__ __launch_bounds__(256) void drho_pairs_kernel(int nbnd, const double*
   }
   __syncthreads();
   cd* dst = part + ((long)k * D1 + x0) * D2 * D3;
-  for (int e = threadIdx.x; e < nbin; e += 256) dst[e] = {bre[e], bim[e]};
+  for (int e = threadIdx.x; e < nbin; e += kRW) dst[e] = {bre[e], bim[e]};
 }
 
 // F_c(l) = sum over the k of chunk c (k = c, c + nchunk, ...) of the part[k]
 // bins b with (org_k + b) = l (mod N) on every axis; then F = sum_c F_c in a
-// fixed order (deterministic, no atomics)
+// fixed order (no atomics in this reduction)
 __global__ __launch_bounds__(256) void drho_reduce_kernel(const cd* __restrict__ part, const int* __restrict__ org,
                                                           int nk, int nchunk, int D1, int D2, int D3, int n1, int n2,
                                                           int n3, cd* __restrict__ Fc) {
@@ -409,7 +428,7 @@ extern "C" pw_status pw_drho(pw_ctx* ckq, const pw_ctx* ck, int nbnd, const doub
     const int nxx = std::min(nx, D[0] - x0);
     const size_t lds = per_x * nxx + tiles + 2 * sizeof(double);
     MKPW_TRY(ensure_lds_limit(ckq, (const void*)drho_pairs_kernel, lds));
-    hipLaunchKernelGGL(drho_pairs_kernel, dim3((unsigned)nk), dim3(256), lds, st, nbnd, d_w, ck->d_npw, ck->d_mkey,
+    hipLaunchKernelGGL(drho_pairs_kernel, dim3((unsigned)nk), dim3(kRW), lds, st, nbnd, d_w, ck->d_npw, ck->d_mkey,
                        ck->npwx, (const cd*)psi_k, ckq->d_npw, ckq->d_mkey, ckq->npwx, (const cd*)dpsi_kq, d_org,
                        D[0], D[1], D[2], x0, nxx, part);
     MKPW_TRY(check_launch(ckq, "drho_pairs", st));

@@ -60,10 +60,11 @@ def _compare(h, ref, sysm, tol):
     return worst / scale
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 4])
 @pytest.mark.parametrize("prec,tol", [(0, TOL64), (1, TOL32)])
 def test_hpsi_c1_all_k(prec, tol, variant):
-    # odd mesh (15^3): the autotuned and the one-line-per-work-item kernels
+    # odd mesh (15^3): the autotuned, the one-line-per-work-item and the
+    # x-convolution kernels
     from paper_2412_01695_amd import mkpw
     cfg = synth.make_config(1)
     torch, s = _system(cfg)
@@ -74,7 +75,7 @@ def test_hpsi_c1_all_k(prec, tol, variant):
     print("C1 rel err", _compare(h, ref, s, tol))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("cid", [2, 3, 4])
 def test_hpsi_k_subset_all_bands(cid, variant):
     # several tiles of the batch with ragged npw: every 8th..64th k of the full list,
@@ -93,7 +94,7 @@ def test_hpsi_k_subset_all_bands(cid, variant):
         print(cid, prec, "rel err", _compare(h, ref, s, tol))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_hpsi_c2_full_batch_sampled(variant):
     # the benchmarked launch (512 k x 20 bands), checked on sampled k-points
     from paper_2412_01695_amd import mkpw
@@ -120,7 +121,7 @@ def test_every_variant_and_workgroup_size(cid):
     vt = ham.vtilde(s.vloc)
     ref = _oracle_rows(cfg, s, vt, psi, range(0, cfg.nk, 2))
     ran = 0
-    for variant in (1, 2, 3):
+    for variant in (1, 2, 3, 4, 5):
         for threads in (256, 512, 1024):
             mkpw.pw_set_option(s.ctx, "hpsi_variant", variant)
             mkpw.pw_set_option(s.ctx, "hpsi_threads", threads)
@@ -154,7 +155,7 @@ def test_other_meshes_every_variant(ecut, n):
     psi = s.psi_guess()
     ref = _oracle_rows(cfg, s, ham.vtilde(s.vloc), psi, range(cfg.nk))
     ran = 0
-    for variant in (0, 1, 2, 3):
+    for variant in (0, 1, 2, 3, 4, 5):
         for threads in ((0,) if variant == 0 else (256, 512, 1024)):
             mkpw.pw_set_option(s.ctx, "hpsi_variant", variant)
             mkpw.pw_set_option(s.ctx, "hpsi_threads", threads)
@@ -243,7 +244,7 @@ def test_repeatable_bitwise():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 def test_slab_widths_agree(variant):
     # every slab width of the lane-pair kernels gives the same result to rounding
     from paper_2412_01695_amd import mkpw
