@@ -48,10 +48,10 @@ PEAK_HBM_GBS = 8000.0
 # sources they were taken on (hash of the files below).
 KERNEL_SOURCES = ("hpsi_kernel.hpp", "fft.hpp", "internal.hpp", "wave.hpp")
 MEASURED_TRAFFIC = {
-    ("fcc1-ecut30-fft24-512k", "fp64", (1, 256, 10)): {
-        "sources": "27d64d7a4f53fc64", "fetch_kib": 36140.1, "write_kib": 51200.0,
+    ("fcc1-ecut40-fft36-1728k", "fp64", (4, 512, 14)): {
+        "sources": "1927c97e7518ea6f", "fetch_kib": 185747.0, "write_kib": 331776.0,
         "fetch_scale": 2.0, "write_scale": 1.0,
-        "profile": "profiles/hpsi_fp64_fcc1-ecut30-fft24-512k.md"},
+        "profile": "profiles/hpsi_fp64_fcc1-ecut40-fft36-1728k.md"},
 }
 
 
