@@ -88,7 +88,9 @@ const char* pw_last_error(const pw_ctx* ctx);
  * as a HIP graph and replay it; 0: launch every kernel of every iteration
  * one by one; the results are the same), "mixed_refine" (default 1: the
  * PW_MIXED Davidson refines in FP64 after its complex64 phase; 0: it returns
- * the complex64-phase result, for measuring what the refinement adds). */
+ * the complex64-phase result, for measuring what the refinement adds),
+ * "cg_switch_digits" (default 10, in [2, 20]: the PW_MIXED CG leaves complex64
+ * once every system's |rho| has fallen by 10^-digits from its start). */
 pw_status pw_set_option(pw_ctx* ctx, const char* key, int64_t value);
 
 /* Read an option (the keys above), or "hpsi_variant_tuned" / "hpsi_slab_tuned" /
@@ -220,8 +222,9 @@ pw_status pw_davidson(pw_ctx* ctx, pw_prec prec, int nbnd, void* psi, double* ei
  * |rho| = |Re <M^-1 r|r>| < thr; converged systems are frozen.
  * iters: host (nk*nrhs) ints (updates applied to each system), may be NULL.
  * PW_MIXED applies H in complex64 while the residual update and all scalars
- * stay FP64, until every system's |rho| has dropped by 1e-10 from its start,
- * then recomputes the residual with H in FP64 and continues to thr.
+ * stay FP64, until every system's |rho| has dropped by 1e-10 from its start
+ * (option "cg_switch_digits"), then recomputes the residual with H in FP64 and
+ * continues to thr.
  * Returns PW_ENOCONV if some system did not converge within max_iter updates
  * (both phases of PW_MIXED together). */
 pw_status pw_dfpt_cg(pw_ctx* ctx, pw_prec prec, int nocc, const void* psi_occ, const double* eps_ha,
@@ -254,6 +257,9 @@ pw_status pw_dfpt_rhs(pw_ctx* ctx_kq, const pw_ctx* ctx_k, int nocc, const void*
  * (nk, nbnd, npwx_k).  dpsi_kq: device complex128 (nk, nbnd, npwx_kq), the
  * solutions of pw_dfpt_cg (in the conduction manifold).  drho_r: device
  * complex128 N1*N2*N3 (C order), written.  1 <= nbnd <= 1024.  FP64.
+ * The pair sums of a k are added into their Miller-difference bins with
+ * atomics, so the order of additions varies: repeated calls agree to rounding,
+ * not bit for bit.
  * PW_EINVAL if the spheres are too large for the difference bins held in LDS
  * (more than about 9000 distinct Miller differences per x-plane). */
 pw_status pw_drho(pw_ctx* ctx_kq, const pw_ctx* ctx_k, int nbnd, const double* wk, const void* psi_k,

@@ -30,6 +30,12 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a) {
   const int nj = sel_i(a.b_cnt, k, a.b_n);
   const int i0 = blockIdx.y * kGT, j0 = blockIdx.z * kGT;
   if (i0 >= ni || j0 >= nj) return;
+  if (a.b_live) {  // a tile none of whose B vectors takes part is skipped
+    const int* lv = a.b_live + (long)k * a.live_kstride;
+    bool any = false;
+    for (int j = j0; j < min(j0 + kGT, nj); ++j) any |= lv[j] != 0;
+    if (!any) return;
+  }
   const int npw = a.npw[k];
   const c64d* A = a.A + (long)k * a.a_kstride + (long)sel_i(a.a_off, k, a.a_row) * a.ld;
   const c64d* B = a.B + (long)k * a.b_kstride + (long)sel_i(a.b_off, k, a.b_row) * a.ld;
@@ -72,7 +78,7 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a) {
     __syncthreads();
   }
   const int i = i0 + ti, j = j0 + tj;
-  if (i < ni && j < nj) {
+  if (i < ni && j < nj && (!a.b_live || a.b_live[(long)k * a.live_kstride + j])) {
     c64d* C = a.C + (long)k * a.c_kstride;
     const int r = sel_i(a.c_roff, k, a.c_row) + i, c = sel_i(a.c_coff, k, a.c_col) + j;
     double vr = a.alpha * sr, vi = a.alpha * si;
@@ -99,7 +105,13 @@ __global__ __launch_bounds__(256) void rows_combine_kernel(CombArgs a) {
   const c64d* Cm = a.Cm + (long)k * a.c_kstride + (long)sel_i(a.c_roff, k, a.c_row) * a.ldc +
                    sel_i(a.c_coff, k, a.c_col);
   __shared__ c64d cs[64][kRJ];
+  const int* lv = a.y_live ? a.y_live + (long)k * a.live_kstride : nullptr;
   for (int j0 = 0; j0 < nj; j0 += kRJ) {
+    if (lv) {  // a pass none of whose output rows takes part is skipped (uniform over the block)
+      bool any = false;
+      for (int jj = j0; jj < min(j0 + kRJ, nj); ++jj) any |= lv[jj] != 0;
+      if (!any) continue;
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < ni * kRJ; e += 256) {
       int i = e / kRJ, jj = e % kRJ;
@@ -121,7 +133,7 @@ __global__ __launch_bounds__(256) void rows_combine_kernel(CombArgs a) {
     }
 #pragma unroll
     for (int jj = 0; jj < kRJ; ++jj) {
-      if (j0 + jj < nj) {
+      if (j0 + jj < nj && (!lv || lv[j0 + jj])) {
         c64d* y = Y + (long)(j0 + jj) * npwx + g;
         c64d o = a.accumulate ? *y : c64d{0.0, 0.0};
         *y = {o.x + a.alpha * ar[jj], o.y + a.alpha * ai[jj]};
@@ -168,28 +180,31 @@ __global__ __launch_bounds__(256) void rows_trmm_kernel(c64d* Yb, long y_kstride
 
 // ------------------------------------------------------------------ precision conversion of row blocks
 
+// (with `live`, row v of k is converted only if live[k * nvec + v])
 __global__ void rows_to_c64_kernel(const c64d* __restrict__ src, long s_kstride, const int* s_off,
                                    cplx<float>* __restrict__ dst, long d_kstride, const int* d_off, const int* cnt,
-                                   int nvec, int npwx) {
+                                   int nvec, int npwx, const int* live) {
   const int k = blockIdx.y;
   const int n = cnt ? cnt[k] : nvec;
   const long total = (long)n * npwx;
   const c64d* s = src + (long)k * s_kstride + (long)(s_off ? s_off[k] : 0) * npwx;
   cplx<float>* d = dst + (long)k * d_kstride + (long)(d_off ? d_off[k] : 0) * npwx;
+  const int* lv = live ? live + (long)k * nvec : nullptr;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
-    d[e] = {(float)s[e].x, (float)s[e].y};
+    if (!lv || lv[e / npwx]) d[e] = {(float)s[e].x, (float)s[e].y};
 }
 
 __global__ void rows_to_c128_kernel(const cplx<float>* __restrict__ src, long s_kstride, const int* s_off,
                                     c64d* __restrict__ dst, long d_kstride, const int* d_off, const int* cnt,
-                                    int nvec, int npwx) {
+                                    int nvec, int npwx, const int* live) {
   const int k = blockIdx.y;
   const int n = cnt ? cnt[k] : nvec;
   const long total = (long)n * npwx;
   const cplx<float>* s = src + (long)k * s_kstride + (long)(s_off ? s_off[k] : 0) * npwx;
   c64d* d = dst + (long)k * d_kstride + (long)(d_off ? d_off[k] : 0) * npwx;
+  const int* lv = live ? live + (long)k * nvec : nullptr;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
-    d[e] = {(double)s[e].x, (double)s[e].y};
+    if (!lv || lv[e / npwx]) d[e] = {(double)s[e].x, (double)s[e].y};
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -217,18 +232,18 @@ pw_status launch_trmm(pw_ctx* c, cplx<double>* Y, long y_kstride, const int* y_o
 }
 
 pw_status launch_to_c64(pw_ctx* c, const cplx<double>* src, long s_kstride, const int* s_off, cplx<float>* dst,
-                        long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st) {
+                        long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st, const int* live) {
   dim3 grid(std::max(1, std::min(64, (nvec * c->npwx + 255) / 256)), c->nk);
   hipLaunchKernelGGL(rows_to_c64_kernel, grid, dim3(256), 0, st, src, s_kstride, s_off, dst, d_kstride, d_off, cnt,
-                     nvec, c->npwx);
+                     nvec, c->npwx, live);
   return check_launch(c, "to_c64", st);
 }
 
 pw_status launch_to_c128(pw_ctx* c, const cplx<float>* src, long s_kstride, const int* s_off, cplx<double>* dst,
-                         long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st) {
+                         long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st, const int* live) {
   dim3 grid(std::max(1, std::min(64, (nvec * c->npwx + 255) / 256)), c->nk);
   hipLaunchKernelGGL(rows_to_c128_kernel, grid, dim3(256), 0, st, src, s_kstride, s_off, dst, d_kstride, d_off,
-                     cnt, nvec, c->npwx);
+                     cnt, nvec, c->npwx, live);
   return check_launch(c, "to_c128", st);
 }
 

@@ -183,10 +183,6 @@ __global__ __launch_bounds__(256) void step2_kernel(cd* t, const cd* d, cd* dold
 
 }  // namespace
 
-// rho reduction (squared M^-1-norm of the residual) at which the mixed mode
-// leaves complex64 H: a residual norm 1e-5 of the starting one, near what an
-// H application with FP32 rounding (relative error ~1e-6) can still resolve
-constexpr double kRelFp32 = 1e-10;
 
 pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const double* eps_h, const double* alpha_h,
                       int nrhs, const cd* b, cd* x, double thr, int max_iter, int32_t* iters_out) {
@@ -238,7 +234,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
 
   bool fp64_h = prec == PW_FP64;
   // t = H v + alpha U (U^H v) for all systems
-  // t = A v; with `live`, H is applied to the active systems only (the others'
+  // t = A v; with `live`, A is applied to the active systems only (the others'
   // t is not read)
   auto apply_a = [&](const cd* v, const int* live) -> pw_status {
     VecSel sel;
@@ -248,9 +244,11 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     if (fp64_h) {
       MKPW_TRY(launch_hpsi(c, PW_FP64, sel, v, t, st));
     } else {
-      MKPW_TRY(launch_to_c64(c, v, (long)nrhs * npwx, nullptr, v32, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
+      MKPW_TRY(
+          launch_to_c64(c, v, (long)nrhs * npwx, nullptr, v32, (long)nrhs * npwx, nullptr, nullptr, nrhs, st, live));
       MKPW_TRY(launch_hpsi(c, PW_MIXED, sel, v32, t32, st));
-      MKPW_TRY(launch_to_c128(c, t32, (long)nrhs * npwx, nullptr, t, (long)nrhs * npwx, nullptr, nullptr, nrhs, st));
+      MKPW_TRY(
+          launch_to_c128(c, t32, (long)nrhs * npwx, nullptr, t, (long)nrhs * npwx, nullptr, nullptr, nrhs, st, live));
     }
     if (gen) MKPW_TRY(launch_spsi(c, PW_FP64, sel, v, t, eps, -1.0, st));  // t -= eps S v
     GramArgs g;
@@ -258,6 +256,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     g.B = v; g.b_kstride = (long)nrhs * npwx; g.b_n = nrhs;
     g.ld = npwx; g.npw = c->d_npw;
     g.C = W; g.c_kstride = (long)nocc * nrhs; g.ldc = nrhs;
+    g.b_live = live; g.live_kstride = nrhs;
     MKPW_TRY(launch_gram(c, g, nocc, nrhs, st));
     hipLaunchKernelGGL(scale_w_kernel, dim3(nk), dim3(256), 0, st, W, nocc * nrhs, alpha);
     MKPW_TRY(check_launch(c, "scale_w", st));
@@ -267,6 +266,7 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
     m.Y = t; m.y_kstride = (long)nrhs * npwx; m.y_n = nrhs;
     m.ld = npwx; m.Cm = W; m.c_kstride = (long)nocc * nrhs; m.ldc = nrhs;
     m.accumulate = 1;
+    m.y_live = live; m.live_kstride = nrhs;
     MKPW_TRY(launch_combine(c, m, nocc, st));
     return PW_OK;
   };
@@ -321,7 +321,10 @@ pw_status dfpt_cg_run(pw_ctx* c, pw_prec prec, int nocc, const cd* U, const doub
   auto step1 = [&](int first) -> pw_status {
     // the FP32 phase of the mixed mode stops at a residual reduction its
     // H application can still resolve; the FP64 phase runs to thr
-    const double rel = fp64_h ? 0.0 : kRelFp32;
+    // rho reduction (squared M^-1-norm of the residual) at which the mixed
+    // mode leaves complex64 H: by default 1e-10, a residual norm 1e-5 of the
+    // starting one, near what an H application with FP32 rounding resolves
+    const double rel = fp64_h ? 0.0 : std::pow(10.0, -(double)c->cg_switch_digits);
     hipLaunchKernelGGL(step1_kernel, dim3((unsigned)nsys), dim3(256), 0, st, r, d, dold, c->d_kin, tk, c->d_npw, npwx,
                        nrhs, rho, rho_old, rho0, active, first, thr, rel, iters_d);
     MKPW_TRY(check_launch(c, "cg_step1", st));

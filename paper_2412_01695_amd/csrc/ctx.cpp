@@ -158,7 +158,8 @@ void clear_q(pw_ctx* c) {
 
 void free_kdata(pw_ctx* c) {
   for (void** p : {(void**)&c->d_npw, (void**)&c->d_nstick, (void**)&c->d_gmap, (void**)&c->d_sof,
-                   (void**)&c->d_kin, (void**)&c->d_mkey, (void**)&c->d_beta64, (void**)&c->d_beta32}) {
+                   (void**)&c->d_kin, (void**)&c->d_mkey, (void**)&c->d_lexperm, (void**)&c->d_beta64,
+                   (void**)&c->d_beta32}) {
     dev_free(c, *p);
     *p = nullptr;
   }
@@ -303,6 +304,9 @@ pw_status pw_set_option(pw_ctx* c, const char* key, int64_t value) {
     c->solver_graph = value != 0;
   } else if (k == "mixed_refine") {
     c->mixed_refine = value != 0;
+  } else if (k == "cg_switch_digits") {
+    if (value < 2 || value > 20) return set_err(c, PW_EINVAL, "cg_switch_digits must be in [2, 20]");
+    c->cg_switch_digits = value;
   } else {
     return set_err(c, PW_EINVAL, "unknown option '" + k + "'");
   }
@@ -324,6 +328,7 @@ pw_status pw_get_option(const pw_ctx* c, const char* key, int64_t* value) {
   else if (k == "tune_log") *value = c->tune_log;
   else if (k == "solver_graph") *value = c->solver_graph;
   else if (k == "mixed_refine") *value = c->mixed_refine;
+  else if (k == "cg_switch_digits") *value = c->cg_switch_digits;
   else if (k == "last_iterations") *value = c->last_iterations;
   else if (k == "last_hpsi_kbands") *value = c->last_hpsi_kbands;
   else if (k == "last_graph_replays") *value = c->last_graph_replays;
@@ -470,6 +475,15 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
       wmax[d] = std::max(wmax[d], mx[d] - mn[d] + 1);
     }
   }
+  c->mlo.assign((size_t)3 * nk, 0);
+  c->mhi.assign((size_t)3 * nk, 0);
+  for (int ik = 0; ik < nk; ++ik)
+    for (int d = 0; d < 3; ++d) {
+      int mx = lo[ik][d];
+      for (auto& p : all[ik]) mx = std::max(mx, p.m[d]);
+      c->mlo[3 * ik + d] = lo[ik][d];
+      c->mhi[3 * ik + d] = mx;
+    }
   for (int d = 0; d < 3; ++d)
     if (wmax[d] > c->fft[d])
       return set_err(c, PW_EINVAL,
@@ -535,6 +549,16 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
       mkey[o] = ((m[0] + 512) << 20) | ((m[1] + 512) << 10) | (m[2] + 512);
     }
     if ((s = upload(c, mkey.data(), mkey.size(), &c->d_mkey)) != PW_OK) return s;
+    // each sphere in lexicographic Miller order (m3 fastest), the packed keys
+    // being monotone in it; the padding maps to itself
+    std::vector<int> lex((size_t)nk * npwx);
+    for (int ik = 0; ik < nk; ++ik) {
+      int* p = lex.data() + (size_t)ik * npwx;
+      const int* key = mkey.data() + (size_t)ik * npwx;
+      for (int i = 0; i < npwx; ++i) p[i] = i;
+      std::sort(p, p + c->npw[ik], [key](int a, int b) { return key[a] < key[b]; });
+    }
+    if ((s = upload(c, lex.data(), lex.size(), &c->d_lexperm)) != PW_OK) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   c->have_k = true;

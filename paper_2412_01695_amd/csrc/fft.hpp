@@ -48,6 +48,15 @@ __host__ __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
 template <class T>
 __host__ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
 
+__host__ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// c + a b as four fused multiply-adds (written out: contraction of the
+// expression form leaves a product, a fused multiply-add and an add per part)
+template <class T>
+__host__ __device__ __forceinline__ cplx<T> cfma(cplx<T> a, cplx<T> b, cplx<T> c) {
+  return {fma_t(-a.y, b.y, fma_t(a.x, b.x, c.x)), fma_t(a.y, b.x, fma_t(a.x, b.y, c.y))};
+}
+
 // ---------------------------------------------------------------- compile-time loops
 
 template <class F, int... Is>

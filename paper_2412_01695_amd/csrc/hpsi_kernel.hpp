@@ -131,7 +131,7 @@ __device__ __forceinline__ void gather_add(const Row<T>& r, int nproj, const lds
       T kk = (T)r.kin[g];
       h.x += kk * v.x;
       h.y += kk * v.y;
-      for (int q = 0; q < nproj; ++q) h = cadd(h, cmul(r.bk[(long)q * r.npwx + g], lds_ld(gam + q)));
+      for (int q = 0; q < nproj; ++q) h = cfma(r.bk[(long)q * r.npwx + g], lds_ld(gam + q), h);
     }
     r.hp[g] = h;
   }
@@ -345,9 +345,9 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
   //         summed over each wave into red[wave][q]
   {
     T ax[kProjChunk], ay[kProjChunk];
-    auto acc = [&](int q, cplx<T> b, cplx<T> v) {
-      ax[q] += b.x * v.x + b.y * v.y;  // conj(b) * v
-      ay[q] += b.x * v.y - b.y * v.x;
+    auto acc = [&](int q, cplx<T> b, cplx<T> v) {  // += conj(b) * v
+      ax[q] = fma_t(b.y, v.y, fma_t(b.x, v.x, ax[q]));
+      ay[q] = fma_t(-b.y, v.x, fma_t(b.x, v.y, ay[q]));
     };
     auto flush = [&](int q0) {
 #pragma unroll
@@ -454,10 +454,7 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
           sfor<WC>([&](auto mp) {
             constexpr int MP = decltype(mp)::value;
             constexpr int M = MP - D;
-            if constexpr (M >= 0 && M < WC) {
-              out[MP].x += tap.x * in[M].x - tap.y * in[M].y;
-              out[MP].y += tap.x * in[M].y + tap.y * in[M].x;
-            }
+            if constexpr (M >= 0 && M < WC) out[MP] = cfma(tap, in[M], out[MP]);
           });
         });
         sfor<WC>([&](auto mm) {

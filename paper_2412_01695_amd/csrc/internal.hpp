@@ -64,6 +64,10 @@ struct GramArgs {
   int c_row = 0, c_col = 0;
   double alpha = 1.0;
   int mirror = 0;
+  // optional: B vector j of k takes part only if b_live[k * live_kstride + j]
+  // (C entries of the others are left as they were)
+  const int* b_live = nullptr;
+  long live_kstride = 0;
 };
 
 // Y_j = [Y_j +] alpha sum_i X_i C(c_row + i, c_col + j) for j < y_cnt, i < x_cnt.
@@ -87,6 +91,9 @@ struct CombArgs {
   int c_row = 0, c_col = 0;
   double alpha = 1.0;
   int accumulate = 0;
+  // optional: output row j of k is formed only if y_live[k * live_kstride + j]
+  const int* y_live = nullptr;
+  long live_kstride = 0;
 };
 
 struct DevMem {
@@ -113,6 +120,7 @@ struct pw_ctx {
   int64_t tune_log = 0;      // print the autotuning timings to stderr
   int64_t solver_graph = 1;  // replay one solver iteration as a captured HIP graph
   int64_t mixed_refine = 1;  // mixed-precision Davidson: refine in FP64 after the complex64 phase
+  int64_t cg_switch_digits = 10;  // mixed-precision CG: leave complex64 once |rho| fell by 10^-digits
   // statistics of the last solver call: iterations run, and k-band rows H was
   // applied to (each (k, vector) row counted once per application)
   int64_t last_iterations = 0, last_hpsi_kbands = 0, last_graph_replays = 0;
@@ -127,6 +135,7 @@ struct pw_ctx {
   std::vector<double> kcart;
   std::vector<int> npw, nstick;
   std::vector<int32_t> miller;  // nk * npwx * 3
+  std::vector<int> mlo, mhi;     // nk * 3: smallest and largest Miller index of each k's sphere per axis
   std::vector<double> kin;      // nk * npwx
   std::vector<int> gmap;        // nk * npwx
   std::vector<short> sof;       // nk * wx * wy
@@ -145,6 +154,7 @@ struct pw_ctx {
   short* d_sof = nullptr;
   double* d_kin = nullptr;
   int* d_mkey = nullptr;    // (nk, npwx) packed Miller index ((m1+512)<<20 | (m2+512)<<10 | (m3+512))
+  int* d_lexperm = nullptr; // (nk, npwx) plane-wave indices of each sphere in lexicographic Miller order
   double v0 = 0.0;          // mean of V(r): its G = 0 Fourier coefficient (Ha)
   double* d_v64 = nullptr;  // V(r) / N_r
   float* d_v32 = nullptr;
@@ -200,10 +210,13 @@ pw_status launch_gram(pw_ctx* c, const GramArgs& a, int ni_max, int nj_max, hipS
 pw_status launch_combine(pw_ctx* c, const CombArgs& a, int ni_max, hipStream_t st);
 pw_status launch_trmm(pw_ctx* c, cplx<double>* Y, long y_kstride, const int* y_off, const int* y_cnt,
                       const cplx<double>* M, long m_kstride, int ldm, hipStream_t st);
+// (with `live`, [nk * nvec], row v of k is converted only if live[k * nvec + v])
 pw_status launch_to_c64(pw_ctx* c, const cplx<double>* src, long s_kstride, const int* s_off, cplx<float>* dst,
-                        long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st);
+                        long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st,
+                        const int* live = nullptr);
 pw_status launch_to_c128(pw_ctx* c, const cplx<float>* src, long s_kstride, const int* s_off, cplx<double>* dst,
-                         long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st);
+                         long d_kstride, const int* d_off, const int* cnt, int nvec, hipStream_t st,
+                         const int* live = nullptr);
 
 // Hermitian eigensolver (Householder tridiagonalization, bisection and inverse
 // iteration, one workgroup per k, LDS):

@@ -13,10 +13,10 @@
 // and needs no mesh in memory:
 //   * dV u is a per-k product of the npw_kq x npw_k matrix dV~[m' - m]
 //     (gathered from the transformed perturbation, which stays in L2) with the
-//     k's bands staged in LDS;
-//   * drho accumulates, per k, M(G1, G2) = sum_nu conj(u(G1)) du(G2) (register
-//     blocked over 4 x 4 pairs, bands staged in LDS) into bins of the Miller
-//     difference d = m_G2 - m_G1 held in LDS; the per-k bins are summed over k
+//     k's bands, on the FP64 matrix cores;
+//   * drho accumulates, per k, M(G1, G2) = sum_nu conj(u(G1)) du(G2) (16 x 16
+//     tiles on the FP64 matrix cores) into bins of the Miller difference
+//     d = m_G2 - m_G1 held in LDS; the per-k bins are summed over k
 //     into the mesh (d mod N; 64 chunks of k summed in parallel, then the
 //     chunks in a fixed order; the per-k bins themselves are summed with LDS
 //     atomics, so results agree to rounding between runs, not bit for bit)
@@ -76,179 +76,292 @@ __global__ __launch_bounds__(256) void mesh_dft_axis_kernel(const cd* __restrict
   out[e] = {scale * sr, scale * si};
 }
 
-constexpr int kVT = 128;  // output plane waves per workgroup
-constexpr int kVG = 64;   // input plane waves staged per step
-constexpr int kVB = 16;   // bands per pass
 
-// out(k, b, G') = scale * sum_G dvt[(m_G' - m_G) mod N] psi(k, b, G)
-__global__ __launch_bounds__(kVT) void dvpsi_kernel(const cd* __restrict__ dvt, int n1, int n2, int n3,
-                                                    const int* __restrict__ npw_in, const int* __restrict__ key_in,
-                                                    int npwx_in, const cd* __restrict__ psi,
-                                                    const int* __restrict__ npw_out, const int* __restrict__ key_out,
-                                                    int npwx_out, cd* __restrict__ out, int nbnd, double scale) {
+// The FP64 matrix cores: D (16 x 16) += A (16 x 4) B (4 x 16), one wave.  A
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; the result element
+// D[4 r + l / 16][l % 16] is component r of the lane's accumulator.
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ mf64x4 mfma_16x16x4(double a, double b, mf64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Linear offset of a Miller triple in a box of sizes (., s2, s3): m1 s2 s3 +
+// m2 s3 + m3.  Differences of such offsets are offsets of Miller differences,
+// so a pair's position in a box that holds every difference is one subtraction.
+__device__ __forceinline__ int miller_lin(int key, int s2, int s3) {
+  int a, b, c;
+  unpack_miller(key, a, b, c);
+  return (a * s2 + b) * s3 + c;
+}
+
+// The transformed perturbation laid out over the box of Miller differences
+// [lo, lo + sz) on each axis: box(d) = dvt(d mod N), so that no index of the
+// pair sum needs a wrap
+__global__ __launch_bounds__(256) void dv_box_kernel(const cd* __restrict__ dvt, int n1, int n2, int n3, int lo1,
+                                                     int lo2, int lo3, int s1, int s2, int s3, cd* __restrict__ box) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)s1 * s2 * s3) return;
+  const int i3 = (int)(e % s3), i2 = (int)((e / s3) % s2), i1 = (int)(e / ((long)s2 * s3));
+  box[e] = dvt[((long)wrap(lo1 + i1, n1) * n2 + wrap(lo2 + i2, n2)) * n3 + wrap(lo3 + i3, n3)];
+}
+
+// rows of psi (nk, nbnd, npwx) with each k's plane waves put in the order
+// perm[k] lists (zero past npw[k])
+__global__ __launch_bounds__(256) void permute_rows_kernel(const cd* __restrict__ psi, const int* __restrict__ perm,
+                                                           const int* __restrict__ npw, int npwx, int nbnd,
+                                                           cd* __restrict__ out) {
   const int k = blockIdx.y;
-  const int gp = blockIdx.x * kVT + threadIdx.x;
-  const int nin = npw_in[k], nout = npw_out[k];
-  __shared__ cd us[kVB][kVG];
-  __shared__ int ms[3][kVG];
-  // mesh index of m_G' - m_G on each axis as (m_G' mod n) + (-m_G mod n),
-  // both in [0, n), less n when the sum reaches n: no division per pair
-  int p1 = 0, p2 = 0, p3 = 0;
-  if (gp < nout) unpack_miller(key_out[(long)k * npwx_out + gp], p1, p2, p3);
-  p1 = wrap(p1, n1);
-  p2 = wrap(p2, n2);
-  p3 = wrap(p3, n3);
-  for (int b0 = 0; b0 < nbnd; b0 += kVB) {
-    double ar[kVB], ai[kVB];
+  const long row = (long)k * nbnd;
+  const int n = npw[k];
+  const int* pk = perm + (long)k * npwx;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < (long)nbnd * npwx; e += (long)gridDim.x * 256) {
+    const int b = (int)(e / npwx), g = (int)(e - (long)b * npwx);
+    out[(row + b) * npwx + g] = g < n ? psi[(row + b) * npwx + pk[g]] : cd{0.0, 0.0};
+  }
+}
+
+constexpr int kDvWaves = 4;  // waves per workgroup of dvpsi_mfma_kernel
+
+// One chunk of U steps of four plane waves for dvpsi_mfma_kernel: this lane's
+// L entry and B values for each step, all loads of the chunk issued before
+// its products (U is chosen so that a chunk holds 16 products).  In the last,
+// partial chunk (TAIL) the loads come from clamped addresses and the L entry
+// of a plane wave past the k sphere is zeroed, which removes its term; a band
+// or row out of range only feeds results that are never stored.
+template <int NG, int U, bool TAIL>
+__device__ __forceinline__ void dv_chunk(const cd* __restrict__ box, const int* wcol, int prow, int nin, int g0,
+                                         int kq, const double* const (&ub)[NG], mf64x4 (&d1)[NG],
+                                         mf64x4 (&d2)[NG]) {
+  int w[U];
 #pragma unroll
-    for (int b = 0; b < kVB; ++b) ar[b] = ai[b] = 0.0;
-    for (int g0 = 0; g0 < nin; g0 += kVG) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < kVB * kVG; e += kVT) {
-        const int b = e / kVG, g = e % kVG;
-        us[b][g] = (b0 + b < nbnd && g0 + g < nin) ? psi[((long)k * nbnd + b0 + b) * npwx_in + g0 + g] : cd{0.0, 0.0};
-      }
-      for (int g = threadIdx.x; g < kVG; g += kVT) {
-        int a = 0, b = 0, c = 0;
-        if (g0 + g < nin) unpack_miller(key_in[(long)k * npwx_in + g0 + g], a, b, c);
-        ms[0][g] = wrap(-a, n1);
-        ms[1][g] = wrap(-b, n2);
-        ms[2][g] = wrap(-c, n3);
-      }
-      __syncthreads();
-      if (gp < nout) {
-        const int ng = min(kVG, nin - g0);
-        for (int g = 0; g < ng; ++g) {
-          int d1 = p1 + ms[0][g], d2 = p2 + ms[1][g], d3 = p3 + ms[2][g];
-          d1 -= d1 >= n1 ? n1 : 0;
-          d2 -= d2 >= n2 ? n2 : 0;
-          d3 -= d3 >= n3 ? n3 : 0;
-          const int idx = (d1 * n2 + d2) * n3 + d3;
-          const cd v = dvt[idx];
+  for (int u = 0; u < U; ++u) {
+    const int g = g0 + 4 * u + kq;
+    w[u] = wcol[TAIL && g >= nin ? 0 : g];
+  }
+  cd a[U];
+  double bv[U][NG];
 #pragma unroll
-          for (int b = 0; b < kVB; ++b) {
-            const cd u = us[b][g];
-            ar[b] += v.x * u.x - v.y * u.y;
-            ai[b] += v.x * u.y + v.y * u.x;
-          }
-        }
-      }
+  for (int u = 0; u < U; ++u) {
+    const int g = g0 + 4 * u + kq;
+    const int gc = TAIL && g >= nin ? 0 : g;
+    a[u] = box[prow + w[u]];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) bv[u][j] = ub[j][2 * gc];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    double xr = a[u].x, xi = a[u].y;
+    if (TAIL && g0 + 4 * u + kq >= nin) xr = xi = 0.0;
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      d1[j] = mfma_16x16x4(xr, bv[u][j], d1[j]);
+      d2[j] = mfma_16x16x4(xi, bv[u][j], d2[j]);
     }
-    if (gp < npwx_out) {
-      for (int b = 0; b < kVB && b0 + b < nbnd; ++b) {
-        cd o = {0.0, 0.0};
-        if (gp < nout) o = {scale * ar[b], scale * ai[b]};
-        out[((long)k * nbnd + b0 + b) * npwx_out + gp] = o;
+  }
+}
+
+// out(k, b, G') = scale * sum_G dvt[(m_G' - m_G) mod N] psi(k, b, G), per k the
+// complex product L (G' x G) U (G x bands), L[G', G] = box(m_G' - m_G), on the
+// matrix cores.  Each wave owns 16 rows G' and NG groups of 8 bands, and sums
+// over G four plane waves per step.  The 16 B columns of a group hold the real
+// parts of its 8 bands, then their imaginary parts, so that two real products
+// per group and step (Re L and Im L against those columns) carry the whole
+// complex product without padding bands; the two halves are combined across
+// lanes at the end.  L entries are gathered from the box (L2-resident) at the
+// row's offset plus the column's, the k's column offsets staged in LDS; the
+// loads of a chunk of U steps are all issued before its products.  Both
+// spheres are walked in lexicographic Miller order (rows through perm_out,
+// columns through perm_in, psi given in that order): the 16 rows of a tile and
+// the 4 columns of a step then mostly run along z, and the 64 entries of a
+// step fall on a few short runs of the box instead of 64 scattered places.
+// Rows G' >= npw of the k+q sphere (the padding) are written as zero.
+template <int NG>
+__global__ __launch_bounds__(kDvWaves * 64) void dvpsi_mfma_kernel(
+    const cd* __restrict__ box, int s2, int s3, int lo1, int lo2, int lo3, const int* __restrict__ npw_in,
+    const int* __restrict__ key_in, const int* __restrict__ perm_in, int npwx_in, const cd* __restrict__ psi,
+    const int* __restrict__ npw_out,
+    const int* __restrict__ key_out, const int* __restrict__ perm_out, int npwx_out, cd* __restrict__ out, int nbnd,
+    double scale) {
+  constexpr int U = 8 / NG;
+  extern __shared__ int wcol[];  // [npwx_in]: -offset of m_G
+  const int k = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nin = npw_in[k], nout = npw_out[k];
+  for (int g = threadIdx.x; g < nin; g += kDvWaves * 64)
+    wcol[g] = -miller_lin(key_in[(long)k * npwx_in + perm_in[(long)k * npwx_in + g]], s2, s3);
+  __syncthreads();
+  const int nbt = (nbnd + 8 * NG - 1) / (8 * NG), ngt = (npwx_out + 15) / 16;
+  const int l16 = lane & 15, kq = lane >> 4, part = l16 >> 3;
+  const int rowoff = ((lo1 * s2) + lo2) * s3 + lo3;
+  const double* pd = reinterpret_cast<const double*>(psi) + (long)k * nbnd * npwx_in * 2 + part;
+  // chunks of U steps; none when either sphere is empty
+  const int nch = nout > 0 ? (nin + 4 * U - 1) / (4 * U) : 0;
+  for (int t = blockIdx.x * kDvWaves + wave; t < ngt * nbt; t += gridDim.x * kDvWaves) {
+    const int gt = t / nbt, bt = t - gt * nbt;
+    // A row of this lane: the G' at position gp of the sphere in Miller
+    // order, so that the 16 rows of a tile run along z and their L entries
+    // are neighbours in the box; a row past the sphere reads the last one (a
+    // valid box offset), its results are not stored
+    const int gp = gt * 16 + l16;
+    const int* pk = perm_out + (long)k * npwx_out;
+    const int prow =
+        nout > 0 ? miller_lin(key_out[(long)k * npwx_out + pk[gp < nout ? gp : nout - 1]], s2, s3) - rowoff : 0;
+    const double* ub[NG];
+    bool colok[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      const int band = bt * 8 * NG + j * 8 + (l16 & 7);
+      colok[j] = band < nbnd;
+      ub[j] = pd + (long)(colok[j] ? band : 0) * npwx_in * 2;
+    }
+    mf64x4 d1[NG], d2[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) d1[j] = d2[j] = mf64x4{0.0, 0.0, 0.0, 0.0};
+    const int nfull = nin / (4 * U);
+    for (int c = 0; c < nfull; ++c) dv_chunk<NG, U, false>(box, wcol, prow, nin, c * 4 * U, kq, ub, d1, d2);
+    if (nfull < nch) dv_chunk<NG, U, true>(box, wcol, prow, nin, nfull * 4 * U, kq, ub, d1, d2);
+    // lane (kq, c), c < 8: D1 and D2 of band column c, its partner lane c + 8
+    // those of the imaginary column: Re = D1[c] - D2[c + 8], Im = D1[c + 8] + D2[c]
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      const int band = bt * 8 * NG + j * 8 + (l16 & 7);
+      cd* ob = out + ((long)k * nbnd + (colok[j] ? band : 0)) * npwx_out;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double o1 = __shfl_xor(d1[j][r], 8, 64), o2 = __shfl_xor(d2[j][r], 8, 64);
+        const int gq = gt * 16 + 4 * r + kq;  // position in Miller order; the padding maps to itself
+        if (part == 0 && colok[j] && gq < npwx_out)
+          ob[pk[gq]] = gq < nout ? cd{scale * (d1[j][r] - o2), scale * (o1 + d2[j][r])} : cd{0.0, 0.0};
       }
     }
   }
 }
 
-constexpr int kRT = 64;    // plane waves of each sphere per pair tile
-constexpr int kRB = 16;    // bands staged per step
-constexpr int kRW = 1024;  // work-items per k-point: a 32 x 32 grid of 2 x 2 pair blocks
+constexpr int kRhoWaves = 16;  // waves per workgroup of drho_mfma_kernel
 
-// Per k: bins F_k(d) += 4 w_k sum_nu conj(u1(G1)) u2(G2) over the pairs with
-// d = m_G2 - m_G1 - org_k in the box [0, D1) x [0, D2) x [0, D3), for the
-// slice x0 <= d1 < x0 + nx held in LDS; the slice is written to part[k].
-// The bins fill most of the LDS, so one workgroup runs per CU: it has 16
-// waves, each work-item summing a 2 x 2 block of pairs of the 64 x 64 tile
-// over the bands staged in LDS, so that enough waves hide the LDS latency.
-// The bins are summed with LDS atomics: the order of the additions into a bin
-// varies from run to run (results agree to rounding, not bit for bit).
-__global__ __launch_bounds__(kRW) void drho_pairs_kernel(int nbnd, const double* __restrict__ wk,
-                                                         const int* __restrict__ npw1, const int* __restrict__ key1,
-                                                         int npwx1, const cd* __restrict__ u1,
-                                                         const int* __restrict__ npw2, const int* __restrict__ key2,
-                                                         int npwx2, const cd* __restrict__ u2,
-                                                         const int* __restrict__ org, int D1, int D2, int D3, int x0,
-                                                         int nx, cd* __restrict__ part) {
-  extern __shared__ char smem[];
+// Per k: bins F_k(d) += 4 w_k M(G1, G2) over the pairs with d = m_G2 - m_G1 -
+// org_k in the box [0, D1) x [0, D2) x [0, D3), for the slice x0 <= d1 < x0 +
+// nx held in LDS (written to part[k]), where M = U1^H U2 (sum over the bands
+// of conj(u1(G1)) u2(G2)) is formed on the matrix cores: each wave takes a
+// contiguous run of 16 x 16 tiles of (G1, G2), row by row, four bands per step
+// (with NBS > 0 the NBS steps of a tile row's U1 entries stay in registers
+// while the row lasts, and the next tile's U2 entries are loaded while this
+// tile is binned), and adds the tile's 256 values into the bins (LDS
+// atomics: the order of the additions into a bin varies from run to run, so
+// results agree to rounding, not bit for bit).  A bin's index is the box
+// offset of m_G2 less that of m_G1 less the k's origin, from per-G offsets
+// staged in LDS after the bins.  One workgroup per k; the bins fill most of a
+// CU's LDS, so a workgroup is as wide as a CU takes to hide latency.
+template <int NBS>
+__global__ __launch_bounds__(kRhoWaves * 64) void drho_mfma_kernel(
+    int nbnd, const double* __restrict__ wk, const int* __restrict__ npw1, const int* __restrict__ key1, int npwx1,
+    const cd* __restrict__ u1, const int* __restrict__ npw2, const int* __restrict__ key2, int npwx2,
+    const cd* __restrict__ u2, const int* __restrict__ org, int D1, int D2, int D3, int x0, int nx,
+    cd* __restrict__ part) {
+  extern __shared__ __align__(16) char smem[];
   const int nbin = nx * D2 * D3;
-  const int nbin_al = (nbin + 1) & ~1;  // keeps the complex tiles 16-byte aligned
+  const int nbin_al = (nbin + 1) & ~1;
   double* bre = reinterpret_cast<double*>(smem);
   double* bim = bre + nbin_al;
-  cd* us = reinterpret_cast<cd*>(bim + nbin_al);  // [kRB][kRT]
-  cd* vs = us + kRB * kRT;                     // [kRB][kRT]
-  int* ma = reinterpret_cast<int*>(vs + kRB * kRT);  // [3][kRT]
-  int* mb = ma + 3 * kRT;                            // [3][kRT]
+  int* o1s = reinterpret_cast<int*>(bim + nbin_al);  // [npwx1]
+  int* o2s = o1s + npwx1;                            // [npwx2]
   const int k = blockIdx.x;
-  for (int e = threadIdx.x; e < nbin; e += kRW) bre[e] = bim[e] = 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < nbin; e += kRhoWaves * 64) bre[e] = bim[e] = 0.0;
   const int n1 = npw1[k], n2 = npw2[k];
+  for (int g = threadIdx.x; g < n1; g += kRhoWaves * 64) o1s[g] = miller_lin(key1[(long)k * npwx1 + g], D2, D3);
+  for (int g = threadIdx.x; g < n2; g += kRhoWaves * 64) o2s[g] = miller_lin(key2[(long)k * npwx2 + g], D2, D3);
+  __syncthreads();
   const double f = 4.0 * wk[k];
-  const int o1 = org[3 * k], o2 = org[3 * k + 1], o3 = org[3 * k + 2];
-  constexpr int kBl = 2;  // pairs per work-item along each sphere
-  const int ti = threadIdx.x >> 5, tj = threadIdx.x & 31;
-  for (int i0 = 0; i0 < n1; i0 += kRT) {
-    for (int j0 = 0; j0 < n2; j0 += kRT) {
-      double cr[kBl][kBl], ci[kBl][kBl];
+  const int base = ((org[3 * k] + x0) * D2 + org[3 * k + 1]) * D3 + org[3 * k + 2];
+  const int nit = (n1 + 15) / 16, njt = (n2 + 15) / 16, ntile = nit * njt;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int t0 = (int)((long)ntile * wave / kRhoWaves), t1 = (int)((long)ntile * (wave + 1) / kRhoWaves);
+  const cd* u1k = u1 + (long)k * nbnd * npwx1;
+  const cd* u2k = u2 + (long)k * nbnd * npwx2;
+  constexpr int NR = NBS > 0 ? NBS : 1;
+  double arc[NR], aic[NR], brc[NR], bic[NR];
+  // B entries of tile t (register path): unconditional loads from clamped
+  // addresses; a band past nbnd meets a zeroed A entry, and a column past the
+  // sphere is never binned
+  auto fetch_b = [&](int t) {
+    const int jt = t - (t / njt) * njt;
+    const int g2 = jt * 16 + l16;
+    const cd* b2 = u2k + (g2 < n2 ? g2 : 0);
 #pragma unroll
-      for (int a = 0; a < kBl; ++a)
+    for (int s = 0; s < NR; ++s) {
+      const int nu = 4 * s + kq;
+      const cd b = b2[(long)(nu < nbnd ? nu : 0) * npwx2];
+      brc[s] = b.x;
+      bic[s] = b.y;
+    }
+  };
+  int cur = -1;
+  if (NBS > 0 && t0 < t1) fetch_b(t0);
+  for (int t = t0; t < t1; ++t) {
+    const int it = t / njt, jt = t - it * njt;
+    const int g1 = it * 16 + l16, g2 = jt * 16 + l16;  // this lane's A row and B column
+    const bool ok1 = g1 < n1, ok2 = g2 < n2;
+    mf64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+    if (NBS > 0) {
+      if (it != cur) {
+        const cd* a1 = u1k + (ok1 ? g1 : 0);
 #pragma unroll
-        for (int c = 0; c < kBl; ++c) cr[a][c] = ci[a][c] = 0.0;
-      for (int b0 = 0; b0 < nbnd; b0 += kRB) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kRB * kRT; e += kRW) {
-          const int b = e / kRT, g = e % kRT;
-          const bool bok = b0 + b < nbnd;
-          us[e] = (bok && i0 + g < n1) ? u1[((long)k * nbnd + b0 + b) * npwx1 + i0 + g] : cd{0.0, 0.0};
-          vs[e] = (bok && j0 + g < n2) ? u2[((long)k * nbnd + b0 + b) * npwx2 + j0 + g] : cd{0.0, 0.0};
+        for (int s = 0; s < NR; ++s) {
+          const int nu = 4 * s + kq;
+          const cd a = a1[(long)(nu < nbnd ? nu : 0) * npwx1];
+          arc[s] = nu < nbnd ? a.x : 0.0;
+          aic[s] = nu < nbnd ? -a.y : 0.0;  // conj(u1); rows past the sphere are never binned
         }
-        if (b0 == 0) {
-          for (int g = threadIdx.x; g < kRT; g += kRW) {
-            int a = 0, b = 0, c = 0;
-            if (i0 + g < n1) unpack_miller(key1[(long)k * npwx1 + i0 + g], a, b, c);
-            ma[g] = a;
-            ma[kRT + g] = b;
-            ma[2 * kRT + g] = c;
-            a = b = c = 0;
-            if (j0 + g < n2) unpack_miller(key2[(long)k * npwx2 + j0 + g], a, b, c);
-            mb[g] = a;
-            mb[kRT + g] = b;
-            mb[2 * kRT + g] = c;
-          }
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int b = 0; b < kRB; ++b) {
-          cd x[kBl], y[kBl];
-#pragma unroll
-          for (int a = 0; a < kBl; ++a) x[a] = us[b * kRT + ti * kBl + a];
-#pragma unroll
-          for (int c = 0; c < kBl; ++c) y[c] = vs[b * kRT + tj * kBl + c];
-#pragma unroll
-          for (int a = 0; a < kBl; ++a)
-#pragma unroll
-            for (int c = 0; c < kBl; ++c) {
-              // conj(x) * y
-              cr[a][c] += x[a].x * y[c].x + x[a].y * y[c].y;
-              ci[a][c] += x[a].x * y[c].y - x[a].y * y[c].x;
-            }
-        }
+        cur = it;
       }
-      // scatter the 2 x 2 block into the bins of this slice
 #pragma unroll
-      for (int a = 0; a < kBl; ++a) {
-        const int g1 = ti * kBl + a;
-        if (i0 + g1 >= n1) continue;
-#pragma unroll
-        for (int c = 0; c < kBl; ++c) {
-          const int g2 = tj * kBl + c;
-          if (j0 + g2 >= n2) continue;
-          const int d1 = mb[g2] - ma[g1] - o1 - x0;
-          if (d1 < 0 || d1 >= nx) continue;
-          const int d2 = mb[kRT + g2] - ma[kRT + g1] - o2;
-          const int d3 = mb[2 * kRT + g2] - ma[2 * kRT + g1] - o3;
-          const int bin = (d1 * D2 + d2) * D3 + d3;
-          atomicAdd(&bre[bin], f * cr[a][c]);
-          atomicAdd(&bim[bin], f * ci[a][c]);
-        }
+      for (int s = 0; s < NR; ++s) {
+        cr = mfma_16x16x4(arc[s], brc[s], cr);
+        cr = mfma_16x16x4(-aic[s], bic[s], cr);
+        ci = mfma_16x16x4(arc[s], bic[s], ci);
+        ci = mfma_16x16x4(aic[s], brc[s], ci);
       }
+      // the next tile's B loads run under this tile's binning
+      if (t + 1 < t1) fetch_b(t + 1);
+    } else {
+      const cd* a1 = u1k + (ok1 ? g1 : 0);
+      const cd* b2 = u2k + (ok2 ? g2 : 0);
+      for (int b0 = 0; b0 < nbnd; b0 += 4) {
+        const int nu = b0 + kq;
+        cd a = {0.0, 0.0}, b = {0.0, 0.0};
+        if (nu < nbnd) {
+          if (ok1) a = a1[(long)nu * npwx1];
+          if (ok2) b = b2[(long)nu * npwx2];
+        }
+        const double ar = a.x, ai = -a.y;  // conj(u1)
+        cr = mfma_16x16x4(ar, b.x, cr);
+        cr = mfma_16x16x4(-ai, b.y, cr);
+        ci = mfma_16x16x4(ar, b.y, ci);
+        ci = mfma_16x16x4(ai, b.x, ci);
+      }
+    }
+    // this lane's results: G1 rows 4 r + kq of the tile, G2 column l16
+    if (!ok2) continue;
+    const int c2 = o2s[g2] - base;
+    int o1v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = it * 16 + 4 * r + kq;
+      o1v[r] = o1s[gr < n1 ? gr : 0];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = it * 16 + 4 * r + kq;
+      const int bin = c2 - o1v[r];
+      if (gr >= n1 || bin < 0 || bin >= nbin) continue;  // past the sphere, or another x-slice of the box
+      atomicAdd(&bre[bin], f * cr[r]);
+      atomicAdd(&bim[bin], f * ci[r]);
     }
   }
   __syncthreads();
   cd* dst = part + ((long)k * D1 + x0) * D2 * D3;
-  for (int e = threadIdx.x; e < nbin; e += kRW) dst[e] = {bre[e], bim[e]};
+  for (int e = threadIdx.x; e < nbin; e += kRhoWaves * 64) dst[e] = {bre[e], bim[e]};
 }
 
 // F_c(l) = sum over the k of chunk c (k = c, c + nchunk, ...) of the part[k]
@@ -307,14 +420,14 @@ pw_status check_pair(pw_ctx* ckq, const pw_ctx* ck) {
 pw_status transform_dv(pw_ctx* c, const double* dv_host, cd* dvt, cd* tmp, hipStream_t st) {
   const int n1 = c->fft[0], n2 = c->fft[1], n3 = c->fft[2];
   const long nr = (long)n1 * n2 * n3;
-  MKPW_HIP(c, hipMemcpyAsync(tmp, dv_host, sizeof(cd) * nr, hipMemcpyHostToDevice, st));
+  HostStage hs(c, st);
+  MKPW_TRY(hs.init(sizeof(cd) * nr, 0));
+  MKPW_HIP(c, hs.up(tmp, (const cd*)dv_host, (size_t)nr));
   const dim3 grid((unsigned)((nr + 255) / 256));
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, tmp, dvt, n1, n2, n3, 0, -1, 1.0);
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, dvt, tmp, n1, n2, n3, 1, -1, 1.0);
   hipLaunchKernelGGL(mesh_dft_axis_kernel, grid, dim3(256), 0, st, tmp, dvt, n1, n2, n3, 2, -1, 1.0 / (double)nr);
   MKPW_TRY(check_launch(c, "mesh_dft", st));
-  // the host array must stay readable until the copy has run
-  MKPW_HIP(c, hipStreamSynchronize(st));
   return PW_OK;
 }
 
@@ -332,6 +445,19 @@ extern "C" pw_status pw_dfpt_rhs(pw_ctx* ckq, const pw_ctx* ck, int nocc, const 
   hipStream_t st = ckq->stream;
   const int nk = ckq->nk;
   const long nr = (long)ckq->fft[0] * ckq->fft[1] * ckq->fft[2];
+  // the box of Miller differences m(k+q) - m(k) over every k (from each
+  // sphere's Miller bounds, kept by pw_set_kpoints)
+  int lo[3], sz[3];
+  for (int a = 0; a < 3; ++a) {
+    int dlo = 1 << 20, dhi = -(1 << 20);
+    for (int k = 0; k < nk; ++k) {
+      dlo = std::min(dlo, ckq->mlo[3 * k + a] - ck->mhi[3 * k + a]);
+      dhi = std::max(dhi, ckq->mhi[3 * k + a] - ck->mlo[3 * k + a]);
+    }
+    lo[a] = dlo;
+    sz[a] = std::max(1, dhi - dlo + 1);
+  }
+  const long nbox = (long)sz[0] * sz[1] * sz[2];
   DevBufs b(ckq);
   cd *dvt, *tmp, *W;
   MKPW_TRY(b.get((size_t)nr, &dvt));
@@ -339,11 +465,33 @@ extern "C" pw_status pw_dfpt_rhs(pw_ctx* ckq, const pw_ctx* ck, int nocc, const 
   MKPW_TRY(b.get((size_t)nk * nocc * nocc, &W));
   MKPW_TRY(transform_dv(ckq, (const double*)dv_r, dvt, tmp, st));
   // rhs0 = -dV u (on the k+q sphere)
+  const int ng = nocc <= 8 ? 1 : nocc <= 16 ? 2 : 4;  // groups of 8 bands per wave
   {
-    const dim3 grid((unsigned)((ckq->npwx + kVT - 1) / kVT), (unsigned)nk);
-    hipLaunchKernelGGL(dvpsi_kernel, grid, dim3(kVT), 0, st, dvt, ckq->fft[0], ckq->fft[1], ckq->fft[2], ck->d_npw,
-                       ck->d_mkey, ck->npwx, (const cd*)psi_k, ckq->d_npw, ckq->d_mkey, ckq->npwx, (cd*)rhs, nocc,
-                       -1.0);
+    // the box of differences for all k, and psi_k with each sphere in Miller
+    // order (with the k+q rows also taken in Miller order, the 64 L entries of
+    // one step are a few runs of neighbours in the box)
+    cd *box, *psi_sorted;
+    MKPW_TRY(b.get((size_t)nbox, &box));
+    MKPW_TRY(b.get((size_t)nk * nocc * ck->npwx, &psi_sorted));
+    hipLaunchKernelGGL(dv_box_kernel, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st, dvt, ckq->fft[0],
+                       ckq->fft[1], ckq->fft[2], lo[0], lo[1], lo[2], sz[0], sz[1], sz[2], box);
+    hipLaunchKernelGGL(permute_rows_kernel,
+                       dim3((unsigned)std::min<long>(64, ((long)nocc * ck->npwx + 255) / 256), (unsigned)nk),
+                       dim3(256), 0, st, (const cd*)psi_k, ck->d_lexperm, ck->d_npw, ck->npwx, nocc, psi_sorted);
+    const int ntile = ((ckq->npwx + 15) / 16) * ((nocc + 8 * ng - 1) / (8 * ng));
+    const dim3 grid((unsigned)((ntile + kDvWaves - 1) / kDvWaves), (unsigned)nk);
+    const size_t lds = sizeof(int) * (size_t)ck->npwx;
+    const void* kern = ng == 1 ? (const void*)dvpsi_mfma_kernel<1>
+                       : ng == 2 ? (const void*)dvpsi_mfma_kernel<2> : (const void*)dvpsi_mfma_kernel<4>;
+    MKPW_TRY(ensure_lds_limit(ckq, kern, lds));
+#define MKPW_DVPSI(NG)                                                                                          \
+  hipLaunchKernelGGL(dvpsi_mfma_kernel<NG>, grid, dim3(kDvWaves * 64), lds, st, box, sz[1], sz[2], lo[0], lo[1], \
+                     lo[2], ck->d_npw, ck->d_mkey, ck->d_lexperm, ck->npwx, (const cd*)psi_sorted, ckq->d_npw,   \
+                     ckq->d_mkey, ckq->d_lexperm, ckq->npwx, (cd*)rhs, nocc, -1.0)
+    if (ng == 1) MKPW_DVPSI(1);
+    else if (ng == 2) MKPW_DVPSI(2);
+    else MKPW_DVPSI(4);
+#undef MKPW_DVPSI
     MKPW_TRY(check_launch(ckq, "dvpsi", st));
   }
   // rhs = rhs0 - S U (U^H rhs0)  =  -(1 - S P_v) dV u
@@ -386,27 +534,19 @@ extern "C" pw_status pw_drho(pw_ctx* ckq, const pw_ctx* ck, int nbnd, const doub
   const int n1 = ckq->fft[0], n2 = ckq->fft[1], n3 = ckq->fft[2];
   const long nr = (long)n1 * n2 * n3;
   // per-k origin of the Miller difference m(k+q) - m(k) and the common box
+  // (from each sphere's Miller bounds, kept by pw_set_kpoints)
   std::vector<int> org(3 * (size_t)nk);
   int D[3] = {1, 1, 1};
   for (int k = 0; k < nk; ++k) {
     for (int a = 0; a < 3; ++a) {
-      int lo1 = 1 << 20, hi1 = -(1 << 20), lo2 = 1 << 20, hi2 = -(1 << 20);
-      for (int g = 0; g < ck->npw[k]; ++g) {
-        const int v = ck->miller[((size_t)k * ck->npwx + g) * 3 + a];
-        lo1 = std::min(lo1, v);
-        hi1 = std::max(hi1, v);
-      }
-      for (int g = 0; g < ckq->npw[k]; ++g) {
-        const int v = ckq->miller[((size_t)k * ckq->npwx + g) * 3 + a];
-        lo2 = std::min(lo2, v);
-        hi2 = std::max(hi2, v);
-      }
+      const int lo1 = ck->mlo[3 * k + a], hi1 = ck->mhi[3 * k + a];
+      const int lo2 = ckq->mlo[3 * k + a], hi2 = ckq->mhi[3 * k + a];
       org[3 * k + a] = lo2 - hi1;
       D[a] = std::max(D[a], hi2 - lo1 - (lo2 - hi1) + 1);
     }
   }
-  // LDS: bins of a slice of the box, the two band tiles and the Miller tiles
-  const size_t tiles = 2 * sizeof(cd) * kRB * kRT + 6 * sizeof(int) * kRT;
+  // LDS: bins of a slice of the box, then the Miller keys of both spheres
+  const size_t tiles = sizeof(int) * (size_t)(ck->npwx + ckq->npwx) + 16;
   const size_t lds_max = 150 * 1024;
   const size_t per_x = 2 * sizeof(double) * (size_t)D[1] * D[2];
   if (per_x + tiles + 2 * sizeof(double) > lds_max) return set_err(ckq, PW_EINVAL, "drho: plane-wave spheres too large for the bins");
@@ -422,15 +562,25 @@ extern "C" pw_status pw_drho(pw_ctx* ckq, const pw_ctx* ck, int nbnd, const doub
   MKPW_TRY(b.get((size_t)nr, &tmp));
   MKPW_TRY(b.get((size_t)3 * nk, &d_org));
   MKPW_TRY(b.get((size_t)nk, &d_w));
-  MKPW_HIP(ckq, hipMemcpyAsync(d_org, org.data(), sizeof(int) * org.size(), hipMemcpyHostToDevice, st));
-  MKPW_HIP(ckq, hipMemcpyAsync(d_w, wk, sizeof(double) * nk, hipMemcpyHostToDevice, st));
+  HostStage hs(ckq, st);
+  MKPW_TRY(hs.init(sizeof(int) * org.size() + sizeof(double) * nk + 512, 0));
+  MKPW_HIP(ckq, hs.up(d_org, org.data(), org.size()));
+  MKPW_HIP(ckq, hs.up(d_w, wk, (size_t)nk));
+  const int nbs = nbnd <= 8 ? 2 : nbnd <= 16 ? 4 : 0;  // band steps held in registers
+  const void* kern = nbs == 2 ? (const void*)drho_mfma_kernel<2>
+                     : nbs == 4 ? (const void*)drho_mfma_kernel<4> : (const void*)drho_mfma_kernel<0>;
   for (int x0 = 0; x0 < D[0]; x0 += nx) {
     const int nxx = std::min(nx, D[0] - x0);
     const size_t lds = per_x * nxx + tiles + 2 * sizeof(double);
-    MKPW_TRY(ensure_lds_limit(ckq, (const void*)drho_pairs_kernel, lds));
-    hipLaunchKernelGGL(drho_pairs_kernel, dim3((unsigned)nk), dim3(kRW), lds, st, nbnd, d_w, ck->d_npw, ck->d_mkey,
-                       ck->npwx, (const cd*)psi_k, ckq->d_npw, ckq->d_mkey, ckq->npwx, (const cd*)dpsi_kq, d_org,
-                       D[0], D[1], D[2], x0, nxx, part);
+    MKPW_TRY(ensure_lds_limit(ckq, kern, lds));
+#define MKPW_DRHO(NBS)                                                                                             \
+  hipLaunchKernelGGL(drho_mfma_kernel<NBS>, dim3((unsigned)nk), dim3(kRhoWaves * 64), lds, st, nbnd, d_w, ck->d_npw, \
+                     ck->d_mkey, ck->npwx, (const cd*)psi_k, ckq->d_npw, ckq->d_mkey, ckq->npwx, (const cd*)dpsi_kq,  \
+                     d_org, D[0], D[1], D[2], x0, nxx, part)
+    if (nbs == 2) MKPW_DRHO(2);
+    else if (nbs == 4) MKPW_DRHO(4);
+    else MKPW_DRHO(0);
+#undef MKPW_DRHO
     MKPW_TRY(check_launch(ckq, "drho_pairs", st));
   }
   const dim3 grid((unsigned)((nr + 255) / 256));

@@ -43,15 +43,17 @@ def _to_lib(s, ik, rows, kp):
     return out
 
 
-@pytest.mark.parametrize("cid,step,overlap", [(1, 1, False), (1, 1, True), (3, 256, True), (4, 288, False)])
-def test_dfpt_rhs_matches_oracle(cid, step, overlap):
+# band counts 5, 12 and 20 take the kernel's one-, two- and four-group tiles
+# (8 bands a group), the last with a partly filled second group
+@pytest.mark.parametrize("cid,step,overlap,nocc", [(1, 1, False, 5), (1, 1, True, 5), (1, 1, False, 12),
+                                                   (1, 1, True, 20), (3, 256, True, 5), (4, 288, False, 12)])
+def test_dfpt_rhs_matches_oracle(cid, step, overlap, nocc):
     from paper_2412_01695_amd import mkpw
     cfg0 = synth.make_config(cid)
     cfg = synth.subset(cfg0, np.arange(0, cfg0.nk, step))
     if overlap:
         cfg = synth.with_overlap(cfg)
     torch, sk, sq = _pair(cfg, synth.q_paper())
-    nocc = 5
     dv = synth.dv_complex_grid(cfg)
     dvt = dft.forward(dv)
     vt = ham.vtilde(sk.vloc)
@@ -77,14 +79,15 @@ def test_dfpt_rhs_matches_oracle(cid, step, overlap):
     assert err <= 1e-12 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("cid,step", [(1, 1), (3, 256), (4, 288)])
-def test_drho_matches_oracle(cid, step):
-    # the 36^3 case holds more Miller differences than one LDS pass: the bins go in slices
+# band counts 6, 12 and 20: two and four band steps held in registers, and
+# the general loop; the 36^3 case holds more Miller differences than one LDS
+# pass, so the bins go in slices
+@pytest.mark.parametrize("cid,step,nb", [(1, 1, 6), (1, 1, 12), (1, 1, 20), (3, 256, 6), (4, 288, 12)])
+def test_drho_matches_oracle(cid, step, nb):
     from paper_2412_01695_amd import mkpw
     cfg0 = synth.make_config(cid)
     cfg = synth.subset(cfg0, np.arange(0, cfg0.nk, step))
     torch, sk, sq = _pair(cfg, synth.q_paper())
-    nb = 6
     u_k = sk.psi_guess(nb)
     du = np.zeros((cfg.nk, nb, sq.npwx), complex)
     for ik in range(cfg.nk):
