@@ -19,125 +19,137 @@ using c64d = cplx<double>;
 
 __device__ __forceinline__ int sel_i(const int* p, int k, int dflt) { return p ? p[k] : dflt; }
 
-// ------------------------------------------------------------------ gram: C = A^H B
+// ------------------------------------------------------------------ gram on the FP64 matrix cores
 
-constexpr int kGT = 16;   // output tile
-constexpr int kGK = 32;   // k-chunk (plane waves) staged in LDS
+// D (16 x 16) += A (16 x 4) B (4 x 16) per wave: lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; item r of the result is D[4 r + l / 16][l % 16]
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ mf64x4 mfma4(double a, double b, mf64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
-__global__ __launch_bounds__(256) void gram_kernel(GramArgs a) {
+constexpr int kMB = 32;  // C block per workgroup (4 waves, one 16 x 16 tile each)
+constexpr int kMK = 32;  // plane waves per chunk staged in LDS
+
+// C = alpha A^H B per k (rows i < a_cnt of A, j < b_cnt of B, inner products
+// over the k's npw plane waves), written at (c_roff + i, c_coff + j), with the
+// products on the matrix cores: the
+// workgroup stages 32 rows of A and of B, 32 plane waves at a time, with
+// coalesced loads into LDS (rows padded by one element against bank
+// conflicts), and each wave forms a 16 x 16 tile, four plane waves per step
+// (four real products per complex step: Re = ar br + ai bi, Im = ar bi - ai br).
+__global__ __launch_bounds__(256) void gram_mfma_kernel(GramArgs a) {
   const int k = blockIdx.x;
   const int ni = sel_i(a.a_cnt, k, a.a_n);
   const int nj = sel_i(a.b_cnt, k, a.b_n);
-  const int i0 = blockIdx.y * kGT, j0 = blockIdx.z * kGT;
+  const int i0 = blockIdx.y * kMB, j0 = blockIdx.z * kMB;
   if (i0 >= ni || j0 >= nj) return;
-  if (a.b_live) {  // a tile none of whose B vectors takes part is skipped
+  if (a.b_live) {  // a block none of whose B vectors takes part is skipped
     const int* lv = a.b_live + (long)k * a.live_kstride;
     bool any = false;
-    for (int j = j0; j < min(j0 + kGT, nj); ++j) any |= lv[j] != 0;
+    for (int j = j0; j < min(j0 + kMB, nj); ++j) any |= lv[j] != 0;
     if (!any) return;
   }
   const int npw = a.npw[k];
   const c64d* A = a.A + (long)k * a.a_kstride + (long)sel_i(a.a_off, k, a.a_row) * a.ld;
   const c64d* B = a.B + (long)k * a.b_kstride + (long)sel_i(a.b_off, k, a.b_row) * a.ld;
-  __shared__ c64d As[kGT][kGK + 1];
-  __shared__ c64d Bs[kGT][kGK + 1];
-  const int tid = threadIdx.x;
-  const int ti = tid / kGT, tj = tid % kGT;
-  double sr = 0.0, si = 0.0;
-  // each work-item stages kGT * kGK / 256 = 2 elements of each tile; the next
-  // chunk's elements are loaded into registers while the current one is used
-  constexpr int kPer = kGT * kGK / 256;
-  c64d na[kPer], nb[kPer];
-  auto fetch = [&](int g0) {
+  __shared__ c64d As[kMB][kMK + 1];
+  __shared__ c64d Bs[kMB][kMK + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ti = wave >> 1, tj = wave & 1;  // this wave's tile of the block
+  const int l16 = lane & 15, kq = lane >> 4;
+  mf64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+  for (int g0 = 0; g0 < npw; g0 += kMK) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * 256, r = e / kGK, g = e % kGK;
-      na[q] = nb[q] = c64d{0.0, 0.0};
-      if (g0 + g < npw) {
-        if (i0 + r < ni) na[q] = A[(long)(i0 + r) * a.ld + g0 + g];
-        if (j0 + r < nj) nb[q] = B[(long)(j0 + r) * a.ld + g0 + g];
-      }
-    }
-  };
-  fetch(0);
-  for (int g0 = 0; g0 < npw; g0 += kGK) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * 256, r = e / kGK, g = e % kGK;
-      As[r][g] = na[q];
-      Bs[r][g] = nb[q];
+    for (int q = 0; q < kMB * kMK / 256; ++q) {
+      const int e = tid + q * 256, r = e / kMK, g = e % kMK;
+      const bool gok = g0 + g < npw;
+      As[r][g] = gok && i0 + r < ni ? A[(long)(i0 + r) * a.ld + g0 + g] : c64d{0.0, 0.0};
+      Bs[r][g] = gok && j0 + r < nj ? B[(long)(j0 + r) * a.ld + g0 + g] : c64d{0.0, 0.0};
     }
     __syncthreads();
-    if (g0 + kGK < npw) fetch(g0 + kGK);
-#pragma unroll 8
-    for (int g = 0; g < kGK; ++g) {
-      c64d x = As[ti][g], y = Bs[tj][g];
-      sr += x.x * y.x + x.y * y.y;
-      si += x.x * y.y - x.y * y.x;
+#pragma unroll
+    for (int kk = 0; kk < kMK; kk += 4) {
+      const c64d x = As[16 * ti + l16][kk + kq], y = Bs[16 * tj + l16][kk + kq];
+      cr = mfma4(x.x, y.x, cr);
+      cr = mfma4(x.y, y.y, cr);
+      ci = mfma4(x.x, y.y, ci);
+      ci = mfma4(-x.y, y.x, ci);
     }
     __syncthreads();
   }
-  const int i = i0 + ti, j = j0 + tj;
-  if (i < ni && j < nj && (!a.b_live || a.b_live[(long)k * a.live_kstride + j])) {
-    c64d* C = a.C + (long)k * a.c_kstride;
-    const int r = sel_i(a.c_roff, k, a.c_row) + i, c = sel_i(a.c_coff, k, a.c_col) + j;
-    double vr = a.alpha * sr, vi = a.alpha * si;
-    C[(long)r * a.ldc + c] = {vr, vi};
+  c64d* C = a.C + (long)k * a.c_kstride;
+  const int r0 = sel_i(a.c_roff, k, a.c_row), c0 = sel_i(a.c_coff, k, a.c_col);
+  const int j = j0 + 16 * tj + l16;
+  if (j >= nj || (a.b_live && !a.b_live[(long)k * a.live_kstride + j])) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + 16 * ti + 4 * r + kq;
+    if (i >= ni) continue;
+    const int row = r0 + i, col = c0 + j;
+    const double vr = a.alpha * cr[r], vi = a.alpha * ci[r];
+    C[(long)row * a.ldc + col] = {vr, vi};
     // mirrored entry, unless that position is itself computed directly
-    const int r0 = sel_i(a.c_roff, k, a.c_row), c0 = sel_i(a.c_coff, k, a.c_col);
-    if (a.mirror && !(c >= r0 && c < r0 + ni && r >= c0 && r < c0 + nj)) C[(long)c * a.ldc + r] = {vr, -vi};
+    if (a.mirror && !(col >= r0 && col < r0 + ni && row >= c0 && row < c0 + nj)) C[(long)col * a.ldc + row] = {vr, -vi};
   }
 }
 
-// ------------------------------------------------------------------ rows_combine
+// ------------------------------------------------------------------ rows_combine on the FP64 matrix cores
 
-constexpr int kRJ = 8;  // output rows per pass
-
-__global__ __launch_bounds__(256) void rows_combine_kernel(CombArgs a) {
+// Y_j = [Y_j +] alpha sum_i X_i C(c_roff + i, c_coff + j) per k, for j <
+// y_cnt, i < x_cnt (at most 64), over all npwx entries of a row, with the
+// products on the matrix cores: a workgroup covers 64 plane waves (16 per
+// wave) and every output row; for each block of 16 output rows the C entries
+// (ni x 16) are staged in LDS, and a wave forms its 16 x 16 tile (output rows
+// x plane waves) four input rows per step, the X entries loaded straight from
+// memory (16 consecutive plane waves of 4 rows per load).
+__global__ __launch_bounds__(256) void rows_combine_mfma_kernel(CombArgs a) {
   const int k = blockIdx.y;
   const int ni = sel_i(a.x_cnt, k, a.x_n);
   const int nj = sel_i(a.y_cnt, k, a.y_n);
   if (nj <= 0) return;
   const int npwx = a.ld;
-  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int g = blockIdx.x * 64 + wave * 16 + l16;  // this lane's B column (plane wave)
+  const bool gok = g < npwx;
   const c64d* X = a.X + (long)k * a.x_kstride + (long)sel_i(a.x_off, k, a.x_row) * npwx;
   c64d* Y = a.Y + (long)k * a.y_kstride + (long)sel_i(a.y_off, k, a.y_row) * npwx;
   const c64d* Cm = a.Cm + (long)k * a.c_kstride + (long)sel_i(a.c_roff, k, a.c_row) * a.ldc +
                    sel_i(a.c_coff, k, a.c_col);
-  __shared__ c64d cs[64][kRJ];
   const int* lv = a.y_live ? a.y_live + (long)k * a.live_kstride : nullptr;
-  for (int j0 = 0; j0 < nj; j0 += kRJ) {
-    if (lv) {  // a pass none of whose output rows takes part is skipped (uniform over the block)
+  __shared__ c64d cs[64][17];  // C(i, j0 + jj), padded
+  for (int j0 = 0; j0 < nj; j0 += 16) {
+    if (lv) {  // a block none of whose output rows takes part is skipped (uniform over the block)
       bool any = false;
-      for (int jj = j0; jj < min(j0 + kRJ, nj); ++jj) any |= lv[jj] != 0;
+      for (int jj = j0; jj < min(j0 + 16, nj); ++jj) any |= lv[jj] != 0;
       if (!any) continue;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < ni * kRJ; e += 256) {
-      int i = e / kRJ, jj = e % kRJ;
-      cs[i][jj] = (j0 + jj < nj) ? Cm[(long)i * a.ldc + j0 + jj] : c64d{0.0, 0.0};
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int i = e / 16, jj = e % 16;
+      cs[i][jj] = i < ni && j0 + jj < nj ? Cm[(long)i * a.ldc + j0 + jj] : c64d{0.0, 0.0};
     }
     __syncthreads();
-    if (g >= npwx) continue;
-    double ar[kRJ], ai[kRJ];
-#pragma unroll
-    for (int jj = 0; jj < kRJ; ++jj) ar[jj] = ai[jj] = 0.0;
-    for (int i = 0; i < ni; ++i) {
-      c64d x = X[(long)i * npwx + g];
-#pragma unroll
-      for (int jj = 0; jj < kRJ; ++jj) {
-        c64d c = cs[i][jj];
-        ar[jj] += x.x * c.x - x.y * c.y;
-        ai[jj] += x.x * c.y + x.y * c.x;
-      }
+    mf64x4 dr = {0.0, 0.0, 0.0, 0.0}, di = {0.0, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < ni; i0 += 4) {
+      const int i = i0 + kq;
+      // A = C^T (row: output j = l16, column: input i = kq); B = X (row i, column g)
+      const c64d c = cs[i][l16];
+      const c64d x = gok && i < ni ? X[(long)i * npwx + g] : c64d{0.0, 0.0};
+      dr = mfma4(c.x, x.x, dr);
+      dr = mfma4(-c.y, x.y, dr);
+      di = mfma4(c.x, x.y, di);
+      di = mfma4(c.y, x.x, di);
     }
+    if (!gok) continue;
 #pragma unroll
-    for (int jj = 0; jj < kRJ; ++jj) {
-      if (j0 + jj < nj && (!lv || lv[j0 + jj])) {
-        c64d* y = Y + (long)(j0 + jj) * npwx + g;
-        c64d o = a.accumulate ? *y : c64d{0.0, 0.0};
-        *y = {o.x + a.alpha * ar[jj], o.y + a.alpha * ai[jj]};
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 + 4 * r + kq;
+      if (j >= nj || (lv && !lv[j])) continue;
+      c64d* y = Y + (long)j * npwx + g;
+      const c64d o = a.accumulate ? *y : c64d{0.0, 0.0};
+      *y = {o.x + a.alpha * dr[r], o.y + a.alpha * di[r]};
     }
   }
 }
@@ -211,15 +223,15 @@ __global__ void rows_to_c128_kernel(const cplx<float>* __restrict__ src, long s_
 
 pw_status launch_gram(pw_ctx* c, const GramArgs& a, int ni_max, int nj_max, hipStream_t st) {
   if (ni_max <= 0 || nj_max <= 0) return PW_OK;
-  dim3 grid(c->nk, (ni_max + kGT - 1) / kGT, (nj_max + kGT - 1) / kGT);
-  hipLaunchKernelGGL(gram_kernel, grid, dim3(256), 0, st, a);
+  dim3 grid(c->nk, (ni_max + kMB - 1) / kMB, (nj_max + kMB - 1) / kMB);
+  hipLaunchKernelGGL(gram_mfma_kernel, grid, dim3(256), 0, st, a);
   return check_launch(c, "gram", st);
 }
 
 pw_status launch_combine(pw_ctx* c, const CombArgs& a, int ni_max, hipStream_t st) {
   if (ni_max > 64) return set_err(c, PW_EINVAL, "rows_combine: more than 64 input rows");
-  dim3 grid((a.ld + 255) / 256, c->nk);
-  hipLaunchKernelGGL(rows_combine_kernel, grid, dim3(256), 0, st, a);
+  dim3 grid((a.ld + 63) / 64, c->nk);
+  hipLaunchKernelGGL(rows_combine_mfma_kernel, grid, dim3(256), 0, st, a);
   return check_launch(c, "rows_combine", st);
 }
 
