@@ -90,7 +90,12 @@ const char* pw_last_error(const pw_ctx* ctx);
  * PW_MIXED Davidson refines in FP64 after its complex64 phase; 0: it returns
  * the complex64-phase result, for measuring what the refinement adds),
  * "cg_switch_digits" (default 10, in [2, 20]: the PW_MIXED CG leaves complex64
- * once every system's |rho| has fallen by 10^-digits from its start). */
+ * once every system's |rho| has fallen by 10^-digits from its start),
+ * "dav_nconv" (default 0 = all: pw_davidson declares a k converged once its
+ * lowest dav_nconv bands are; the bands above are buffer bands, corrected
+ * while the k runs but not waited for, and their results may be less
+ * accurate.  A block whose top band is nearly degenerate with the next
+ * eigenvalue converges that band slowly; a few buffer bands remove that). */
 pw_status pw_set_option(pw_ctx* ctx, const char* key, int64_t value);
 
 /* Read an option (the keys above), or "hpsi_variant_tuned" / "hpsi_slab_tuned" /
@@ -193,7 +198,8 @@ pw_status pw_s_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* s
  * each stopping on its own.
  * psi: device complex128 (nk, nbnd, npwx): starting vectors in, eigenvectors
  * out (S-orthonormal).  eig_ha: host (nk, nbnd) doubles, eigenvalues in Ha.
- * A k-point is converged when every band's eigenvalue changed by less than
+ * A k-point is converged when every band's (with option "dav_nconv", every
+ * one of the lowest dav_nconv bands') eigenvalue changed by less than
  * tol_ry/2 Ha in the last iteration and its residual norm |H psi - e S psi| is
  * below 1e-5 (so the eigenvalue error is of order residual^2 / gap).
  * iters, converged: host (nk) ints, may be NULL.

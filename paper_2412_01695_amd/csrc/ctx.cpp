@@ -304,6 +304,9 @@ pw_status pw_set_option(pw_ctx* c, const char* key, int64_t value) {
     c->solver_graph = value != 0;
   } else if (k == "mixed_refine") {
     c->mixed_refine = value != 0;
+  } else if (k == "dav_nconv") {
+    if (value < 0 || value > 1024) return set_err(c, PW_EINVAL, "dav_nconv must be in [0, 1024]");
+    c->dav_nconv = value;
   } else if (k == "cg_switch_digits") {
     if (value < 2 || value > 20) return set_err(c, PW_EINVAL, "cg_switch_digits must be in [2, 20]");
     c->cg_switch_digits = value;
@@ -329,6 +332,7 @@ pw_status pw_get_option(const pw_ctx* c, const char* key, int64_t* value) {
   else if (k == "solver_graph") *value = c->solver_graph;
   else if (k == "mixed_refine") *value = c->mixed_refine;
   else if (k == "cg_switch_digits") *value = c->cg_switch_digits;
+  else if (k == "dav_nconv") *value = c->dav_nconv;
   else if (k == "last_iterations") *value = c->last_iterations;
   else if (k == "last_hpsi_kbands") *value = c->last_hpsi_kbands;
   else if (k == "last_graph_replays") *value = c->last_graph_replays;
@@ -414,8 +418,10 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
   struct PW {
     double q2;
     int m[3];
+    int gen;  // position in the lexicographic (m1, m2, m3) enumeration
   };
   std::vector<std::vector<PW>> all(nk);
+  std::vector<std::vector<int>> lexpos(nk);  // per k: sorted position of the j-th G in Miller order
   // spheres of the k-points built and sorted in parallel host threads, each
   // over its own range of k
   auto build_range = [&](int k0, int k1) {
@@ -437,12 +443,15 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
           double q[3];
           for (int d = 0; d < 3; ++d) q[d] = kk[d] + m1 * b[d] + m2 * b[3 + d] + m3 * b[6 + d];
           double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
-          if (q2 < c->ecut_ry) v.push_back({q2, {m1, m2, m3}});
+          if (q2 < c->ecut_ry) v.push_back({q2, {m1, m2, m3}, (int)v.size()});
         }
     std::sort(v.begin(), v.end(), [](const PW& x, const PW& y) {
       if (x.q2 != y.q2) return x.q2 < y.q2;
       return std::lexicographical_compare(x.m, x.m + 3, y.m, y.m + 3);
     });
+    auto& lp = lexpos[ik];
+    lp.resize(v.size());
+    for (size_t i = 0; i < v.size(); ++i) lp[v[i].gen] = (int)i;
   }
   };
   {
@@ -549,14 +558,14 @@ pw_status pw_set_kpoints(pw_ctx* c, int nk, const double* k, int32_t* npw_out, i
       mkey[o] = ((m[0] + 512) << 20) | ((m[1] + 512) << 10) | (m[2] + 512);
     }
     if ((s = upload(c, mkey.data(), mkey.size(), &c->d_mkey)) != PW_OK) return s;
-    // each sphere in lexicographic Miller order (m3 fastest), the packed keys
-    // being monotone in it; the padding maps to itself
+    // each sphere in lexicographic Miller order (m3 fastest, the order the
+    // spheres were enumerated in); the padding maps to itself
     std::vector<int> lex((size_t)nk * npwx);
     for (int ik = 0; ik < nk; ++ik) {
       int* p = lex.data() + (size_t)ik * npwx;
-      const int* key = mkey.data() + (size_t)ik * npwx;
-      for (int i = 0; i < npwx; ++i) p[i] = i;
-      std::sort(p, p + c->npw[ik], [key](int a, int b) { return key[a] < key[b]; });
+      const int n = c->npw[ik];
+      std::copy(lexpos[ik].begin(), lexpos[ik].end(), p);
+      for (int i = n; i < npwx; ++i) p[i] = i;
     }
     if ((s = upload(c, lex.data(), lex.size(), &c->d_lexperm)) != PW_OK) return s;
     HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -200,11 +200,14 @@ __global__ void dav_reset_kernel(int nk, int nbnd, int* nb, int* nnc, int* activ
 
 // After the residuals (Sec. 2.1): a band needs a correction unless its
 // eigenvalue moved by less than etol and its residual norm is below rtol; a
-// k with no such band is converged and frozen.  The bands that need one are
+// k none of whose lowest nconv bands needs one is converged and frozen (with
+// nconv < nbnd the bands above are buffer bands: corrected while the k runs,
+// which speeds up the bands below when the spectrum is nearly degenerate at
+// the top of the block, but not waited for).  The bands that need one are
 // listed in map[k][0 .. nnc), and a k whose basis would outgrow nbmax (or
 // whose last block was dropped) restarts from its Ritz vectors (flag, nb =
 // nbnd).  One wave per k, lane j = band j.
-__global__ __launch_bounds__(64) void dav_decide_kernel(int nbnd, int nbmax, double etol, double rtol,
+__global__ __launch_bounds__(64) void dav_decide_kernel(int nbnd, int nconv, int nbmax, double etol, double rtol,
                                                         const double* __restrict__ theta, const double* __restrict__ rn,
                                                         double* th_old, int* active, int* nb, int* nnc, int* flag,
                                                         int* map, int* force_restart, int* iters, int* nactive) {
@@ -227,8 +230,11 @@ __global__ __launch_bounds__(64) void dav_decide_kernel(int nbnd, int nbmax, dou
   if (todo) map[(long)k * nbnd + __popcll(m & ((1ull << j) - 1ull))] = j;
   if (j == 0) {
     const int cnt = __popcll(m);
+    // the k is done once its lowest nconv bands are (buffer bands above them
+    // are corrected while it runs, but need not converge)
+    const unsigned long long need = nconv >= 64 ? ~0ull : (1ull << nconv) - 1ull;
     iters[k] += 1;
-    if (cnt == 0) {
+    if ((m & need) == 0) {
       active[k] = 0;
       nnc[k] = 0;
       flag[k] = 0;
@@ -298,6 +304,7 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   const double tol = 0.5 * tol_ry;  // Ha
   const double rtol64 = 1e-5;
   const double tol32 = std::max(tol, 2e-6), rtol32 = 2e-4;
+  const int nconv = c->dav_nconv > 0 && c->dav_nconv < nbnd ? (int)c->dav_nconv : nbnd;
   const bool gen = c->have_q;  // generalized problem: S != 1
   c->last_iterations = c->last_hpsi_kbands = c->last_graph_replays = 0;
   DevBufs b(c);
@@ -537,7 +544,7 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
                          T, Rb, rn);
       MKPW_TRY(check_launch(c, "resid", st));
     }
-    hipLaunchKernelGGL(dav_decide_kernel, dim3(nk), dim3(64), 0, st, nbnd, nbmax, etol, rtol, theta, rn, th_old,
+    hipLaunchKernelGGL(dav_decide_kernel, dim3(nk), dim3(64), 0, st, nbnd, nconv, nbmax, etol, rtol, theta, rn, th_old,
                        d_active, d_nb, d_nnc, d_flag, d_map, d_force, d_iters, d_nact);
     MKPW_TRY(check_launch(c, "decide", st));
     {

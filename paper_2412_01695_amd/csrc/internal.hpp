@@ -9,35 +9,9 @@
 
 #include "mkpw.h"  // include/ is on the include path
 #include "fft.hpp"
+#include "hpsi_types.hpp"
 
 namespace mkpw {
-
-// Per-k tables the H|psi> kernels read (device pointers) plus the launch shape.
-// The plane waves of k live in a W1 x W2 x W3 window of Miller indices
-// shifted to start at 0 (m' = m - min m); a "stick" is one (m1', m2') pair
-// that holds at least one plane wave.
-struct KTables {
-  int nk = 0, npwx = 0;
-  int n1 = 0, n2 = 0, n3 = 0;
-  int wx = 0, wy = 0, wz = 0;  // window extents (max over k)
-  int smax = 0;                // max sticks per k
-  const int* npw = nullptr;      // [nk]
-  const int* nstick = nullptr;   // [nk]
-  const int* gmap = nullptr;     // [nk * npwx]   (stick << 8) | m3'
-  const short* sof = nullptr;    // [nk * wx * wy] stick index of (m1', m2') or -1
-  const double* kin = nullptr;   // [nk * npwx]   |k+G|^2 / 2 (Ha)
-};
-
-// Which vectors to apply H to: for k, vectors [off[k], off[k] + cnt[k]) of a
-// (nk, kstride) array of rows of length npwx; cnt == nullptr means all k use
-// [0, nvec).
-struct VecSel {
-  int nvec = 0;             // grid extent in the band direction (max count)
-  long kstride = 0;         // elements between consecutive k
-  const int* off = nullptr; // [nk] or null
-  const int* cnt = nullptr; // [nk] or null
-  const int* live = nullptr;  // [nk * nvec] nonzero for rows to compute, or null (rows left unwritten)
-};
 
 // C = alpha A^H B over row blocks: A rows [a_off, a_off + a_cnt) of a
 // (nk, *, ld) array, likewise B; C(k) is a ldc-strided matrix, written at
@@ -121,6 +95,7 @@ struct pw_ctx {
   int64_t solver_graph = 1;  // replay one solver iteration as a captured HIP graph
   int64_t mixed_refine = 1;  // mixed-precision Davidson: refine in FP64 after the complex64 phase
   int64_t cg_switch_digits = 10;  // mixed-precision CG: leave complex64 once |rho| fell by 10^-digits
+  int64_t dav_nconv = 0;          // Davidson: bands that must converge (0: all; the rest are buffer bands)
   // statistics of the last solver call: iterations run, and k-band rows H was
   // applied to (each (k, vector) row counted once per application)
   int64_t last_iterations = 0, last_hpsi_kbands = 0, last_graph_replays = 0;

@@ -207,10 +207,13 @@ def gapped(cfg: Config, scale: float = 32.0, nocc: int = 8) -> Config:
     opens a gap above band `nocc` over the whole Brillouin zone (an insulator):
     for the two-atom cell, scale 32 leaves about 0.3 Ha between bands 8 and 9
     over the k and k+q lists at the paper's q, so that the DFPT systems at
-    q != 0 are positive definite on the conduction states."""
+    q != 0 are positive definite on the conduction states.  `nb_solve` is the
+    band count for the eigensolver: nocc + 4, the three above the first empty
+    band being buffer bands (at some k bands 9 and 10, or 12 and 13, come
+    within 0.002 Ha, which slows the convergence of the top band of a block)."""
     c = Config(cfg.name.replace("fcc2", f"fcc2x{scale:g}") + f"-nocc{nocc}", cfg.lat, cfg.ecut_ry, cfg.fft,
                cfg.kpts, cfg.nbnd, cfg.tau, cfg.projectors, cfg.dij, cfg.seed,
-               dict(cfg.extra, vloc_scale=float(scale), nocc=nocc, nrhs=nocc), cfg.qij)
+               dict(cfg.extra, vloc_scale=float(scale), nocc=nocc, nrhs=nocc, nb_solve=nocc + 4), cfg.qij)
     return c
 
 

@@ -158,7 +158,7 @@ def test_shape_options(mk):
     ctx = mk.pw_create(-1, None)
     for key, good, bad in (("hpsi_variant", (0, 1, 2, 3, 4, 5), (-1, 6)), ("hpsi_threads", (0, 256, 512, 1024), (128, 300)),
                            ("hpsi_slab", (0, 1, 36), (-1, 513)), ("tune_log", (0, 1), ()),
-                           ("cg_switch_digits", (2, 10, 20), (1, 21))):
+                           ("cg_switch_digits", (2, 10, 20), (1, 21)), ("dav_nconv", (0, 8, 1024), (-1, 1025))):
         for v in good:
             mk.pw_set_option(ctx, key, v)
             assert mk.pw_get_option(ctx, key) == v
