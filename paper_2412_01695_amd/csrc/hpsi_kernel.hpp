@@ -436,11 +436,50 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
       // X[d] = sum_l1 V(l1)/N_r exp(-2 pi i d l1 / N) the line's taps, read
       // from xt[l3][d + WC - 1][l2]; a work-item owns one line, in place
       constexpr int DW = 2 * WC - 1;
+      // the compact x convolution holds about 100 fewer registers; it is the
+      // faster one in FP32, and it keeps the 1024-work-item kernels from
+      // spilling, while the FP64 ones at 256 and 512 work-items run faster
+      // with every tap loaded up front
+      constexpr bool XCOMPACT = sizeof(T) == 4 || NT >= 1024;
       const cplx<T>* xt = reinterpret_cast<const cplx<T>*>(vr);
       for (int i = tid; i < N * nl; i += NT) {
         const int lcn = i / N, l2 = i - lcn * N;
         lc* y = Y + lcn * wx * YS + l2;
         const cplx<T>* tp = xt + (long)(l30 + lcn) * DW * N + l2;
+        if constexpr (XCOMPACT) {
+        // compact form: the inputs m in order, each read from LDS and added
+        // into the outputs with the taps X[m' - m], so that only the outputs,
+        // the input and the WC taps in use are live: a tap enters at the
+        // first input that reaches it (every tap for m = 0, then the tap of
+        // the first output) and leaves WC inputs later; a scheduling fence
+        // per input keeps the compiler from loading ahead.  The line is
+        // transformed in place, so all its outputs are formed before any is
+        // stored.  (The arrays live in a lambda of their own: declared in the
+        // loop body they come out with 55 more registers and spills.)
+        [&] {
+        cplx<T> out[WC], tap[DW];
+        sfor<WC>([&](auto o) { out[decltype(o)::value] = zero; });
+        sfor<WC>([&](auto mm) {
+          constexpr int M = decltype(mm)::value;
+          if (M < wx) {
+            const cplx<T> x = lds_ld(y + M * YS);
+            sfor<WC>([&](auto o) {
+              constexpr int MP = decltype(o)::value;
+              constexpr int DD = MP - M + (WC - 1);  // tap index of m' - m
+              if constexpr (M == 0 || MP == 0) tap[DD] = tp[(long)DD * N];
+              out[MP] = cfma(tap[DD], x, out[MP]);
+            });
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        });
+        sfor<WC>([&](auto o) {
+          constexpr int MP = decltype(o)::value;
+          if (MP < wx) lds_st(y + MP * YS, out[MP]);
+        });
+        }();
+        } else {
+        // all taps at once: the inputs and outputs in registers, every tap
+        // loaded once and applied to the outputs it reaches
         cplx<T> in[WC], out[WC];
         sfor<WC>([&](auto mm) {
           constexpr int M = decltype(mm)::value;
@@ -461,6 +500,7 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
           constexpr int M = decltype(mm)::value;
           if (M < wx) lds_st(y + M * YS, out[M]);
         });
+        }
       }
     } else {
     // x lines: W inputs -> N points -> * V/N_r -> forward -> W outputs
