@@ -78,13 +78,18 @@ __device__ __forceinline__ void make_reflector(cd x, int mm, int lane, double& g
   }
 }
 
+// The matrix is kept as its lower triangle, packed by rows (entry (i, j), i >=
+// j, at i (i + 1) / 2 + j): the Hermitian reduction only updates the lower
+// part of the trailing block and stores each reflector below the diagonal.
+__device__ __forceinline__ int pk(int i, int j) { return (i * (i + 1) >> 1) + j; }
+constexpr int kEigPacked = kEigMax * (kEigMax + 1) / 2;
+
+// LDS: the packed matrix, then for nev eigenpairs the rows Y (eigenvectors of
+// T_r) and U (two elimination rows per eigenpair), which the back-transformed
+// eigenvectors Z (nev x kEigLd complex, fewer bytes) overwrite at the end,
+// then the fixed part below.  At nev <= 24 the whole stays under 80 KiB, so
+// two workgroups share a CU.
 struct EigLds {
-  cd A[kEigMax * kEigLd];                  // matrix, then the reflectors below the diagonal
-  double Y[kEigNev * kEigYs];              // eigenvectors of T_r, one row per eigenpair
-  union {
-    double U[3 * kEigNev * kEigYs];        // per-lane elimination rows (u0, u1, u2)
-    cd Z[kEigNev * kEigLd];                // eigenvectors of A being back-transformed
-  };
   cd ecx[kEigMax];                         // complex subdiagonal of T
   cd ph[kEigMax];                          // phases D
   cd pw[kEigMax];                          // p, then w of the current reflector
@@ -95,6 +100,13 @@ struct EigLds {
   double scal[4];
 };
 
+__host__ __device__ constexpr size_t eig_region_bytes(int nev) {
+  return ((size_t)3 * nev * kEigYs * sizeof(double) + 15) & ~(size_t)15;
+}
+__host__ __device__ constexpr size_t eig_lds_bytes(int nev) {
+  return sizeof(cd) * kEigPacked + eig_region_bytes(nev) + sizeof(EigLds);
+}
+
 __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict__ Ag, long a_kstride, int lda,
                                                     const int* __restrict__ nk_arr, int nev_req,
                                                     double* __restrict__ w, cd* __restrict__ Vg, long v_kstride,
@@ -104,14 +116,18 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
   if (n <= 0) return;
   const int nev = min(nev_req, n);
   extern __shared__ __align__(16) unsigned char smem[];
-  EigLds& S = *reinterpret_cast<EigLds*>(smem);
-  cd* A = S.A;
+  cd* A = reinterpret_cast<cd*>(smem);                         // packed lower triangle
+  double* Yr = reinterpret_cast<double*>(A + kEigPacked);      // [nev][kEigYs]
+  double* Ur = Yr + (size_t)nev_req * kEigYs;                  // [2 nev][kEigYs]
+  cd* Zr = reinterpret_cast<cd*>(Yr);                          // [nev][kEigLd], at the end
+  EigLds& S = *reinterpret_cast<EigLds*>(smem + sizeof(cd) * kEigPacked + eig_region_bytes(nev_req));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const cd* Ak = Ag + (long)k * a_kstride;
   for (int e = tid; e < n * n; e += kEigThreads) {
     const int i = e / n, j = e - (e / n) * n;
+    if (j > i) continue;
     const cd a = Ak[(long)i * lda + j], b = Ak[(long)j * lda + i];  // exact Hermitian part
-    A[i * kEigLd + j] = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+    A[pk(i, j)] = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
   }
   __syncthreads();
 
@@ -121,11 +137,11 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
   //         forms its reflector from the new values held in registers.
   if (wave == 0 && n >= 3) {
     cd x = {0.0, 0.0};
-    if (lane < n - 1) x = A[(1 + lane) * kEigLd];
+    if (lane < n - 1) x = A[pk(1 + lane, 0)];
     double g0;
     cd beta, u;
     make_reflector(x, n - 1, lane, g0, beta, u);
-    if (lane < n - 1) A[(1 + lane) * kEigLd] = u;
+    if (lane < n - 1) A[pk(1 + lane, 0)] = u;
     if (lane == 0) {
       S.g[0] = g0;
       S.ecx[0] = beta;
@@ -142,7 +158,10 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
       if (r < m) {
         const int i = j + 1 + r;
         for (int l = q; l < m; l += kEigPQ) {
-          const cd a = A[i * kEigLd + j + 1 + l], u = A[(j + 1 + l) * kEigLd + j];
+          // A[i][c] from the lower triangle, conjugated above the diagonal
+          const int c = j + 1 + l;
+          const cd al = c <= i ? A[pk(i, c)] : A[pk(c, i)];
+          const cd a = {al.x, c <= i ? al.y : -al.y}, u = A[pk(c, j)];
           acc.x += a.x * u.x - a.y * u.y;
           acc.y += a.x * u.y + a.y * u.x;
         }
@@ -161,16 +180,16 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
       cd p = {0.0, 0.0}, u = {0.0, 0.0};
       if (lane < m) {
         p = S.pw[lane];
-        u = A[(j + 1 + lane) * kEigLd + j];
+        u = A[pk(j + 1 + lane, j)];
       }
       kk = 0.5 * gj * wave_sum64(u.x * p.x + u.y * p.y);
     }
     if (wave == 0) {
       // column j+1 of the trailing block (row j+1+lane), updated in registers
       cd a = {0.0, 0.0};
-      if (lane < m) a = A[(j + 1 + lane) * kEigLd + j + 1];
+      if (lane < m) a = A[pk(j + 1 + lane, j + 1)];
       if (gj != 0.0 && lane < m) {
-        const cd ur = A[(j + 1 + lane) * kEigLd + j], u0 = A[(j + 1) * kEigLd + j];
+        const cd ur = A[pk(j + 1 + lane, j)], u0 = A[pk(j + 1, j)];
         const cd pr = S.pw[lane], p0 = S.pw[0];
         const cd wr = {pr.x - kk * ur.x, pr.y - kk * ur.y}, w0 = {p0.x - kk * u0.x, p0.y - kk * u0.y};
         // a -= u_r conj(w_0) + w_r conj(u_0)
@@ -192,17 +211,19 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
           S.ecx[j + 1] = beta;
         }
       }
-      if (lane < m) A[(j + 1 + lane) * kEigLd + j + 1] = st;
+      if (lane < m) A[pk(j + 1 + lane, j + 1)] = st;
     }
     if (gj != 0.0) {
-      // the rest of the trailing block (columns j+2 ..): A -= u w^H + w u^H
+      // the rest of the trailing block (columns j+2 .., lower triangle):
+      // A -= u w^H + w u^H
       const int mc = m - 1;
       for (int e = tid; e < m * mc; e += kEigThreads) {
         const int r = e / mc, l = 1 + e - (e / mc) * mc;
-        const cd ur = A[(j + 1 + r) * kEigLd + j], ul = A[(j + 1 + l) * kEigLd + j];
+        if (l > r) continue;
+        const cd ur = A[pk(j + 1 + r, j)], ul = A[pk(j + 1 + l, j)];
         const cd pr = S.pw[r], pl = S.pw[l];
         const cd wr = {pr.x - kk * ur.x, pr.y - kk * ur.y}, wl = {pl.x - kk * ul.x, pl.y - kk * ul.y};
-        cd& av = A[(j + 1 + r) * kEigLd + j + 1 + l];
+        cd& av = A[pk(j + 1 + r, j + 1 + l)];
         // u_r conj(w_l) + w_r conj(u_l)
         av.x -= ur.x * wl.x + ur.y * wl.y + wr.x * ul.x + wr.y * ul.y;
         av.y -= ur.y * wl.x - ur.x * wl.y + wr.y * ul.x - wr.x * ul.y;
@@ -218,9 +239,9 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
     const int i = lane;
     double di = 0.0, mag = 0.0;
     cd u = {1.0, 0.0};
-    if (i < n) di = A[i * kEigLd + i].x;
+    if (i < n) di = A[pk(i, i)].x;
     if (i + 1 < n) {
-      const cd ei = i == n - 2 ? A[(n - 1) * kEigLd + n - 2] : S.ecx[i];  // the last one has no reflector
+      const cd ei = i == n - 2 ? A[pk(n - 1, n - 2)] : S.ecx[i];  // the last one has no reflector
       if (i == n - 2) S.ecx[i] = ei;
       mag = sqrt(ei.x * ei.x + ei.y * ei.y);
       if (mag > 0.0) u = {ei.x / mag, ei.y / mag};
@@ -303,11 +324,12 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
     const int t = lane;
     if (t < nev) {
       const double lm = S.lam[t];
-      // inverse iteration on T_r - lm, rows kept in U[(3 t + c) * kEigYs + i]
-      double* y = S.Y + t * kEigYs;
-      double* u0 = S.U + (3 * t + 0) * kEigYs;
-      double* u1 = S.U + (3 * t + 1) * kEigYs;
-      double* u2 = S.U + (3 * t + 2) * kEigYs;
+      // inverse iteration on T_r - lm, rows kept in U[(2 t + c) * kEigYs + i];
+      // the third elimination row is e_{i+1} where row i was pivoted (bit i
+      // of `swapped`) and zero elsewhere, so it is not stored
+      double* y = Yr + t * kEigYs;
+      double* u0 = Ur + (2 * t + 0) * kEigYs;
+      double* u1 = Ur + (2 * t + 1) * kEigYs;
       const double tiny = 2.2e-16 * fmax(nrm, 1e-300);
       unsigned h = 0x9E3779B9u * (unsigned)(t + 1);
       for (int i = 0; i < n; ++i) {  // fixed pseudo-random start in [-1, 1)
@@ -319,13 +341,13 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
       for (int iter = 0; iter < 3; ++iter) {
         // forward elimination with partial pivoting, right-hand side y
         double c0 = S.d[0] - lm, c1 = n > 1 ? S.e[0] : 0.0, rc = y[0];
+        unsigned long long swapped = 0;
         for (int i = 0; i + 1 < n; ++i) {
           const double s = S.e[i], dd = S.d[i + 1] - lm, ee = i + 2 < n ? S.e[i + 1] : 0.0, b1 = y[i + 1];
           if (fabs(c0) >= fabs(s)) {
             const double l = c0 != 0.0 ? s * rcp_nr(c0) : 0.0;
             u0[i] = c0;
             u1[i] = c1;
-            u2[i] = 0.0;
             y[i] = rc;
             c0 = dd - l * c1;
             c1 = ee;
@@ -334,7 +356,7 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
             const double l = c0 * rcp_nr(s);
             u0[i] = s;
             u1[i] = dd;
-            u2[i] = ee;
+            swapped |= 1ull << i;  // third row entry ee
             y[i] = b1;
             const double n0 = c1 - l * dd;
             c1 = -l * ee;
@@ -349,7 +371,8 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
         for (int i = n - 1; i >= 0; --i) {
           double piv = u0[i];
           if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
-          const double v = (y[i] - (i + 1 < n ? u1[i] * y1 : 0.0) - (i + 2 < n ? u2[i] * y2 : 0.0)) * rcp_nr(piv);
+          const double u2i = i + 2 < n && ((swapped >> i) & 1ull) ? S.e[i + 1] : 0.0;
+          const double v = (y[i] - (i + 1 < n ? u1[i] * y1 : 0.0) - (i + 2 < n ? u2i * y2 : 0.0)) * rcp_nr(piv);
           y[i] = v;
           y2 = y1;
           y1 = v;
@@ -374,11 +397,11 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
   // component i of every vector, so only the wave sums cross lanes
   if (wave == 0) {
     for (int t2 = 0; t2 < nev; ++t2) {
-      double* yt = S.Y + t2 * kEigYs;
+      double* yt = Yr + t2 * kEigYs;
       double v = lane < n ? yt[lane] : 0.0;
       for (int pass = 0; pass < 2; ++pass) {
         for (int s2 = S.cstart[t2]; s2 < t2; ++s2) {
-          const double ys = lane < n ? S.Y[s2 * kEigYs + lane] : 0.0;
+          const double ys = lane < n ? Yr[s2 * kEigYs + lane] : 0.0;
           v -= wave_sum64(ys * v) * ys;
         }
         const double nn = wave_sum64(v * v);
@@ -398,14 +421,15 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
 #pragma unroll
     for (int s2 = 0; s2 < kPerWave; ++s2) {
       const int t = wave + kEigWaves * s2;
-      const double yv = (t < nev && lane < n) ? S.Y[t * kEigYs + lane] : 0.0;
+      const double yv = (t < nev && lane < n) ? Yr[t * kEigYs + lane] : 0.0;
       zi[s2] = lane < n ? cd{S.ph[lane].x * yv, S.ph[lane].y * yv} : cd{0.0, 0.0};
     }
+    __syncthreads();  // Z overwrites Y: every wave has its rows in registers first
     for (int j = n - 3; j >= 0; --j) {
       const double gj = S.g[j];
       if (gj == 0.0) continue;
       cd u = {0.0, 0.0};
-      if (lane > j && lane < n) u = A[lane * kEigLd + j];
+      if (lane > j && lane < n) u = A[pk(lane, j)];
       double cr[kPerWave], ci[kPerWave];
 #pragma unroll
       for (int s2 = 0; s2 < kPerWave; ++s2) {
@@ -423,7 +447,7 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
 #pragma unroll
     for (int s2 = 0; s2 < kPerWave; ++s2) {
       const int t = wave + kEigWaves * s2;
-      if (t < nev && lane < n) S.Z[t * kEigLd + lane] = zi[s2];
+      if (t < nev && lane < n) Zr[t * kEigLd + lane] = zi[s2];
     }
   }
   __syncthreads();
@@ -431,7 +455,7 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
   cd* Vk = Vg + (long)k * v_kstride;
   for (int e = tid; e < n * nev; e += kEigThreads) {
     const int r = e / nev, t = e - (e / nev) * nev;
-    Vk[(long)r * ldv + t] = S.Z[t * kEigLd + r];
+    Vk[(long)r * ldv + t] = Zr[t * kEigLd + r];
   }
 }
 
@@ -508,7 +532,7 @@ pw_status launch_heev(pw_ctx* c, const cd* A, long a_kstride, int lda, const int
                       cd* V, long v_kstride, int ldv, hipStream_t st) {
   if (nmax > kEigMax) return set_err(c, PW_EINVAL, "reduced problem larger than 64");
   if (nev > kEigNev) return set_err(c, PW_EINVAL, "more than 32 eigenpairs requested");
-  const size_t lds = sizeof(EigLds);
+  const size_t lds = eig_lds_bytes(nev);
   {
     pw_status s = ensure_lds_limit(c, (const void*)heevx_kernel, lds);
     if (s != PW_OK) return s;
