@@ -169,7 +169,11 @@ pw_status pw_init_guess(pw_ctx* ctx, int nbnd, uint64_t seed, void* psi);
  * V(r) -> forward 3D FFT with 1/N_r -> gather) and nonlocal
  * sum_pq beta_p D_pq <beta_q|psi> (Eqs. lambdah, gamma, finalnl).
  * psi and hpsi: device, (nk, nbnd, npwx); complex128 for PW_FP64,
- * complex64 for PW_MIXED; they must not overlap. */
+ * complex64 for PW_MIXED; they must not overlap.
+ * The transforms are compiled for cubic meshes N^3 with N in {15, 18, 20, 24,
+ * 30, 32, 36} (the 2,3,5-smooth sizes of cutoffs up to about 60 Ry for cells
+ * like the workloads here); any other mesh is refused with PW_EINVAL, as every
+ * entry point that applies H does. */
 pw_status pw_h_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* hpsi);
 
 /* pw_h_psi for callers that cannot allocate device memory (code under HIP
@@ -195,7 +199,10 @@ pw_status pw_s_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* s
 
 /* Lowest nbnd eigenpairs of H psi = eps S psi at every k by block Davidson
  * (Sec. 2.1; S = 1 without an overlap), all k-points advancing together,
- * each stopping on its own.
+ * each stopping on its own.  1 <= nbnd <= 32 (else PW_EINVAL); the basis
+ * holds at most min(4 nbnd, 64) vectors per k (the reduced problems are
+ * solved in LDS; option "davidson_basis_factor" sets the 4), and a k whose
+ * next block would exceed it restarts from its Ritz vectors.
  * psi: device complex128 (nk, nbnd, npwx): starting vectors in, eigenvectors
  * out (S-orthonormal).  eig_ha: host (nk, nbnd) doubles, eigenvalues in Ha.
  * A k-point is converged when every band's (with option "dav_nconv", every
