@@ -58,6 +58,9 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ti = wave >> 1, tj = wave & 1;  // this wave's tile of the block
   const int l16 = lane & 15, kq = lane >> 4;
+  // a wave whose tile lies wholly past ni or nj (small blocks) stages its
+  // share of the chunk but forms no products
+  const bool live = i0 + 16 * ti < ni && j0 + 16 * tj < nj;
   mf64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
   for (int g0 = 0; g0 < npw; g0 += kMK) {
 #pragma unroll
@@ -69,7 +72,7 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramArgs a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kMK; kk += 4) {
+    for (int kk = 0; kk < kMK && live; kk += 4) {
       const c64d x = As[16 * ti + l16][kk + kq], y = Bs[16 * tj + l16][kk + kq];
       cr = mfma4(x.x, y.x, cr);
       cr = mfma4(x.y, y.y, cr);

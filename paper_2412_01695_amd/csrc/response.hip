@@ -123,15 +123,19 @@ __global__ __launch_bounds__(256) void permute_rows_kernel(const cd* __restrict_
 constexpr int kDvWaves = 4;  // waves per workgroup of dvpsi_mfma_kernel
 
 // One chunk of U steps of four plane waves for dvpsi_mfma_kernel: this lane's
-// L entry and B values for each step, all loads of the chunk issued before
-// its products (U is chosen so that a chunk holds 16 products).  In the last,
-// partial chunk (TAIL) the loads come from clamped addresses and the L entry
-// of a plane wave past the k sphere is zeroed, which removes its term; a band
-// or row out of range only feeds results that are never stored.
+// L entry for each step (gathered from the box) and its B values (from the
+// block of psi staged in LDS: row j of `bl` holds plane waves [b0, b0 + KC)
+// of the lane's band of group j, real and imaginary parts interleaved, `part`
+// already added, so plane wave g is element 2 (g - b0)), all loads of the
+// chunk issued before its products (U is chosen so that a chunk holds 16
+// products).  In the last, partial chunk (TAIL) a plane wave past the k
+// sphere reads element 0 and box offset 0 and its L entry is zeroed, which
+// removes its term; a band or row out of range only feeds results that are
+// never stored.
 template <int NG, int U, bool TAIL>
-__device__ __forceinline__ void dv_chunk(const cd* __restrict__ box, const int* wcol, int prow, int nin, int g0,
-                                         int kq, const double* const (&ub)[NG], mf64x4 (&d1)[NG],
-                                         mf64x4 (&d2)[NG]) {
+__device__ __forceinline__ void dv_chunk_lds(const cd* __restrict__ box, const int* wcol, int prow, int nin, int g0,
+                                             int b0, int kq, const double* const (&bl)[NG], mf64x4 (&d1)[NG],
+                                             mf64x4 (&d2)[NG]) {
   int w[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -143,10 +147,10 @@ __device__ __forceinline__ void dv_chunk(const cd* __restrict__ box, const int* 
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int g = g0 + 4 * u + kq;
-    const int gc = TAIL && g >= nin ? 0 : g;
+    const int gl = TAIL && g >= nin ? 0 : g - b0;
     a[u] = box[prow + w[u]];
 #pragma unroll
-    for (int j = 0; j < NG; ++j) bv[u][j] = ub[j][2 * gc];
+    for (int j = 0; j < NG; ++j) bv[u][j] = bl[j][2 * gl];
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -160,20 +164,30 @@ __device__ __forceinline__ void dv_chunk(const cd* __restrict__ box, const int* 
   }
 }
 
+// plane waves of psi staged in LDS per step of dvpsi_mfma_kernel: 8 NG bands
+// x kDvKC(NG) plane waves, 33 KiB for two buffers whatever NG
+__host__ __device__ constexpr int dv_kc(int ng) { return 128 / ng; }
+__host__ __device__ constexpr size_t dv_lds_bytes(int ng, int npwx_in) {
+  return sizeof(cd) * 2 * (size_t)(8 * ng) * (dv_kc(ng) + 1) + sizeof(int) * (size_t)npwx_in;
+}
+
 // out(k, b, G') = scale * sum_G dvt[(m_G' - m_G) mod N] psi(k, b, G), per k the
 // complex product L (G' x G) U (G x bands), L[G', G] = box(m_G' - m_G), on the
-// matrix cores.  Each wave owns 16 rows G' and NG groups of 8 bands, and sums
-// over G four plane waves per step.  The 16 B columns of a group hold the real
-// parts of its 8 bands, then their imaginary parts, so that two real products
-// per group and step (Re L and Im L against those columns) carry the whole
-// complex product without padding bands; the two halves are combined across
-// lanes at the end.  L entries are gathered from the box (L2-resident) at the
-// row's offset plus the column's, the k's column offsets staged in LDS; the
-// loads of a chunk of U steps are all issued before its products.  Both
+// matrix cores.  A workgroup takes four tiles of 16 rows G' (one per wave)
+// and one group of 8 NG bands, and sums over G four plane waves per step.
+// The 16 B columns of a band group hold the real parts of its 8 bands, then
+// their imaginary parts, so that two real products per group and step (Re L
+// and Im L against those columns) carry the whole complex product without
+// padding bands; the two halves are combined across lanes at the end.  L
+// entries are gathered from the box (L2-resident) at the row's offset plus
+// the column's, the k's column offsets staged in LDS; the B values come from
+// blocks of psi staged in LDS (two buffers, one barrier per block) that the
+// four waves share, so that a step costs one vector load (the gather) and
+// the loads of a chunk of U steps are all issued before its products.  Both
 // spheres are walked in lexicographic Miller order (rows through perm_out,
-// columns through perm_in, psi given in that order): the 16 rows of a tile and
-// the 4 columns of a step then mostly run along z, and the 64 entries of a
-// step fall on a few short runs of the box instead of 64 scattered places.
+// columns through perm_in, psi given in that order): the 16 rows of a tile
+// and the 4 columns of a step then mostly run along z, and the 64 entries of
+// a step fall on a few short runs of the box instead of 64 scattered places.
 // Rows G' >= npw of the k+q sphere (the padding) are written as zero.
 template <int NG>
 __global__ __launch_bounds__(kDvWaves * 64) void dvpsi_mfma_kernel(
@@ -183,57 +197,67 @@ __global__ __launch_bounds__(kDvWaves * 64) void dvpsi_mfma_kernel(
     const int* __restrict__ key_out, const int* __restrict__ perm_out, int npwx_out, cd* __restrict__ out, int nbnd,
     double scale) {
   constexpr int U = 8 / NG;
-  extern __shared__ int wcol[];  // [npwx_in]: -offset of m_G
+  constexpr int NB = 8 * NG;        // bands of a group
+  constexpr int KC = dv_kc(NG);     // plane waves per staged block
+  constexpr int BS = KC + 1;        // padded row of a staged band (bank spread)
+  extern __shared__ __align__(16) char smem[];
+  cd* Bs = reinterpret_cast<cd*>(smem);                    // [2][NB][BS]
+  int* wcol = reinterpret_cast<int*>(Bs + 2 * NB * BS);    // [npwx_in]: -offset of m_G
   const int k = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nin = npw_in[k], nout = npw_out[k];
   for (int g = threadIdx.x; g < nin; g += kDvWaves * 64)
     wcol[g] = -miller_lin(key_in[(long)k * npwx_in + perm_in[(long)k * npwx_in + g]], s2, s3);
   __syncthreads();
-  const int nbt = (nbnd + 8 * NG - 1) / (8 * NG), ngt = (npwx_out + 15) / 16;
+  const int nbt = (nbnd + NB - 1) / NB, ngt = (npwx_out + 15) / 16, ngg = (ngt + kDvWaves - 1) / kDvWaves;
   const int l16 = lane & 15, kq = lane >> 4, part = l16 >> 3;
   const int rowoff = ((lo1 * s2) + lo2) * s3 + lo3;
-  const double* pd = reinterpret_cast<const double*>(psi) + (long)k * nbnd * npwx_in * 2 + part;
-  // chunks of U steps; none when either sphere is empty
-  const int nch = nout > 0 ? (nin + 4 * U - 1) / (4 * U) : 0;
-  for (int t = blockIdx.x * kDvWaves + wave; t < ngt * nbt; t += gridDim.x * kDvWaves) {
-    const int gt = t / nbt, bt = t - gt * nbt;
+  const int* pk = perm_out + (long)k * npwx_out;
+  const cd* psik = psi + (long)k * nbnd * npwx_in;
+  for (int wg = blockIdx.x; wg < ngg * nbt; wg += gridDim.x) {  // uniform over the workgroup
+    const int gg = wg / nbt, bt = wg - gg * nbt;
+    const int gt = gg * kDvWaves + wave;  // past the last tile: joins the staging, stores nothing
     // A row of this lane: the G' at position gp of the sphere in Miller
-    // order, so that the 16 rows of a tile run along z and their L entries
-    // are neighbours in the box; a row past the sphere reads the last one (a
-    // valid box offset), its results are not stored
+    // order; a row past the sphere reads the last one (a valid box offset),
+    // its results are not stored
     const int gp = gt * 16 + l16;
-    const int* pk = perm_out + (long)k * npwx_out;
     const int prow =
         nout > 0 ? miller_lin(key_out[(long)k * npwx_out + pk[gp < nout ? gp : nout - 1]], s2, s3) - rowoff : 0;
-    const double* ub[NG];
-    bool colok[NG];
-#pragma unroll
-    for (int j = 0; j < NG; ++j) {
-      const int band = bt * 8 * NG + j * 8 + (l16 & 7);
-      colok[j] = band < nbnd;
-      ub[j] = pd + (long)(colok[j] ? band : 0) * npwx_in * 2;
-    }
     mf64x4 d1[NG], d2[NG];
 #pragma unroll
     for (int j = 0; j < NG; ++j) d1[j] = d2[j] = mf64x4{0.0, 0.0, 0.0, 0.0};
-    const int nfull = nin / (4 * U);
-    for (int c = 0; c < nfull; ++c) dv_chunk<NG, U, false>(box, wcol, prow, nin, c * 4 * U, kq, ub, d1, d2);
-    if (nfull < nch) dv_chunk<NG, U, true>(box, wcol, prow, nin, nfull * 4 * U, kq, ub, d1, d2);
+    for (int b0 = 0, buf = 0; b0 < nin && nout > 0; b0 += KC, buf ^= 1) {
+      cd* bb = Bs + buf * NB * BS;
+      for (int e = threadIdx.x; e < NB * KC; e += kDvWaves * 64) {
+        const int bl = e / KC, g = e - bl * KC;
+        const int band = bt * NB + bl;
+        bb[bl * BS + g] = band < nbnd && b0 + g < nin ? psik[(long)band * npwx_in + b0 + g] : cd{0.0, 0.0};
+      }
+      __syncthreads();
+      const double* bl[NG];
+#pragma unroll
+      for (int j = 0; j < NG; ++j) bl[j] = reinterpret_cast<const double*>(bb + (j * 8 + (l16 & 7)) * BS) + part;
+      const int kc = min(KC, nin - b0), nfull = kc / (4 * U);
+      for (int c = 0; c < nfull; ++c)
+        dv_chunk_lds<NG, U, false>(box, wcol, prow, nin, b0 + c * 4 * U, b0, kq, bl, d1, d2);
+      if (nfull * 4 * U < kc) dv_chunk_lds<NG, U, true>(box, wcol, prow, nin, b0 + nfull * 4 * U, b0, kq, bl, d1, d2);
+    }
     // lane (kq, c), c < 8: D1 and D2 of band column c, its partner lane c + 8
     // those of the imaginary column: Re = D1[c] - D2[c + 8], Im = D1[c + 8] + D2[c]
 #pragma unroll
     for (int j = 0; j < NG; ++j) {
-      const int band = bt * 8 * NG + j * 8 + (l16 & 7);
-      cd* ob = out + ((long)k * nbnd + (colok[j] ? band : 0)) * npwx_out;
+      const int band = bt * NB + j * 8 + (l16 & 7);
+      const bool colok = band < nbnd;
+      cd* ob = out + ((long)k * nbnd + (colok ? band : 0)) * npwx_out;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const double o1 = __shfl_xor(d1[j][r], 8, 64), o2 = __shfl_xor(d2[j][r], 8, 64);
         const int gq = gt * 16 + 4 * r + kq;  // position in Miller order; the padding maps to itself
-        if (part == 0 && colok[j] && gq < npwx_out)
+        if (part == 0 && colok && gq < npwx_out)
           ob[pk[gq]] = gq < nout ? cd{scale * (d1[j][r] - o2), scale * (o1 + d2[j][r])} : cd{0.0, 0.0};
       }
     }
+    __syncthreads();  // the next group's first block reuses buffer 0
   }
 }
 
@@ -478,9 +502,9 @@ extern "C" pw_status pw_dfpt_rhs(pw_ctx* ckq, const pw_ctx* ck, int nocc, const 
     hipLaunchKernelGGL(permute_rows_kernel,
                        dim3((unsigned)std::min<long>(64, ((long)nocc * ck->npwx + 255) / 256), (unsigned)nk),
                        dim3(256), 0, st, (const cd*)psi_k, ck->d_lexperm, ck->d_npw, ck->npwx, nocc, psi_sorted);
-    const int ntile = ((ckq->npwx + 15) / 16) * ((nocc + 8 * ng - 1) / (8 * ng));
-    const dim3 grid((unsigned)((ntile + kDvWaves - 1) / kDvWaves), (unsigned)nk);
-    const size_t lds = sizeof(int) * (size_t)ck->npwx;
+    const int ngt = (ckq->npwx + 15) / 16, nbt = (nocc + 8 * ng - 1) / (8 * ng);
+    const dim3 grid((unsigned)(((ngt + kDvWaves - 1) / kDvWaves) * nbt), (unsigned)nk);
+    const size_t lds = dv_lds_bytes(ng, ck->npwx);
     const void* kern = ng == 1 ? (const void*)dvpsi_mfma_kernel<1>
                        : ng == 2 ? (const void*)dvpsi_mfma_kernel<2> : (const void*)dvpsi_mfma_kernel<4>;
     MKPW_TRY(ensure_lds_limit(ckq, kern, lds));
