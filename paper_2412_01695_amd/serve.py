@@ -33,6 +33,41 @@ from . import mkpw, synth
 _VLOC_CACHE = {}
 _VLOC_LOCK = threading.Lock()
 
+# host threads for the projector tables of a request (numpy releases the
+# interpreter lock in the array work, so the chunks run in parallel)
+_BETA_POOL = None
+_BETA_POOL_LOCK = threading.Lock()
+
+
+def _beta_pool():
+    global _BETA_POOL
+    with _BETA_POOL_LOCK:
+        if _BETA_POOL is None:
+            from concurrent.futures import ThreadPoolExecutor
+            _BETA_POOL = ThreadPoolExecutor(max_workers=8, thread_name_prefix="beta")
+        return _BETA_POOL
+
+
+def projector_table(cfg, npw, npwx, mall, kchunk=128):
+    """beta_p(k+G) in the library's (nk, nproj, npwx) layout, zero padded, from
+    the concatenated Miller indices of every k (library order), built in
+    chunks of k-points on host threads."""
+    beta = np.zeros((cfg.nk, cfg.nproj, npwx), dtype=np.complex128)
+    off = np.concatenate([[0], np.cumsum(npw)]).astype(np.int64)
+    b = synth.reciprocal_rows(cfg.lat)
+
+    def chunk(k0):
+        k1 = min(cfg.nk, k0 + kchunk)
+        n = np.asarray(npw[k0:k1])
+        kl = np.repeat(np.arange(k1 - k0), n)
+        m = mall[off[k0]:off[k1]]
+        q = cfg.kpts[k0:k1][kl] + m.astype(np.float64) @ b
+        pos = np.arange(m.shape[0]) - np.repeat(off[k0:k1] - off[k0], n)
+        beta[k0 + kl, :, pos] = synth.beta_values(cfg, q).T
+
+    list(_beta_pool().map(chunk, range(0, cfg.nk, kchunk)))
+    return beta
+
 
 def _vloc(cfg):
     # V(r) depends on the mesh and the atoms only (the model potential's
@@ -175,19 +210,9 @@ class Server:
             mkpw.pw_set_cutoff(ctx, cfg.ecut_ry, cfg.fft)
             npw, npwx = mkpw.pw_set_kpoints(ctx, cfg.kpts)
             mkpw.pw_set_vloc(ctx, _vloc(cfg))
-            # projector values at every k+G of the library's order, all k at once
+            # projector values at every k+G of the library's order
             mall = mkpw.pw_get_miller_all(ctx, npw)
-            kidx = np.repeat(np.arange(cfg.nk), npw)
-            q = cfg.kpts[kidx] + mall.astype(np.float64) @ synth.reciprocal_rows(cfg.lat)
-            bv = synth.beta_values(cfg, q)                     # (nproj, sum npw)
-            # (nk, nproj, npwx) with zero padding: each k's rows are a contiguous
-            # run of the concatenated plane waves
-            beta = np.zeros((cfg.nk, cfg.nproj, npwx), dtype=np.complex128)
-            flat = (kidx * (cfg.nproj * npwx) + (np.arange(mall.shape[0]) - np.repeat(np.cumsum(npw) - npw, npw)))
-            bf = beta.reshape(-1)
-            for p in range(cfg.nproj):
-                bf[flat + p * npwx] = bv[p]
-            mkpw.pw_set_projectors(ctx, beta, cfg.dij)
+            mkpw.pw_set_projectors(ctx, projector_table(cfg, npw, npwx, mall), cfg.dij)
             t1 = time.monotonic()
             with torch.cuda.stream(stream):
                 d_psi = torch.empty((cfg.nk, cfg.nbnd, npwx), dtype=torch.complex128, device=f"cuda:{self.device}")
