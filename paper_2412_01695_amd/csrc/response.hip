@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -290,7 +291,9 @@ __global__ __launch_bounds__(kRhoWaves * 64) void drho_mfma_kernel(
   int* o1s = reinterpret_cast<int*>(bim + nbin_al);  // [npwx1]
   int* o2s = o1s + npwx1;                            // [npwx2]
   const int k = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave index made wave-uniform for the compiler, so that the tile walk runs
+  // on the scalar unit
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int e = threadIdx.x; e < nbin; e += kRhoWaves * 64) bre[e] = bim[e] = 0.0;
   const int n1 = npw1[k], n2 = npw2[k];
   for (int g = threadIdx.x; g < n1; g += kRhoWaves * 64) o1s[g] = miller_lin(key1[(long)k * npwx1 + g], D2, D3);
@@ -304,12 +307,14 @@ __global__ __launch_bounds__(kRhoWaves * 64) void drho_mfma_kernel(
   const cd* u1k = u1 + (long)k * nbnd * npwx1;
   const cd* u2k = u2 + (long)k * nbnd * npwx2;
   constexpr int NR = NBS > 0 ? NBS : 1;
-  double arc[NR], aic[NR], brc[NR], bic[NR];
-  // B entries of tile t (register path): unconditional loads from clamped
-  // addresses; a band past nbnd meets a zeroed A entry, and a column past the
-  // sphere is never binned
-  auto fetch_b = [&](int t) {
-    const int jt = t - (t / njt) * njt;
+  // with the A entries in registers the weight f is folded into them
+  const double fb = NBS > 0 ? 1.0 : f;
+  double arc[NR], aic[NR], naic[NR], brc[NR], bic[NR];
+  int o1v[4];
+  // B entries of tile column jt (register path): unconditional loads from
+  // clamped addresses; a band past nbnd meets a zeroed A entry, and a column
+  // past the sphere is never binned
+  auto fetch_b = [&](int jt) {
     const int g2 = jt * 16 + l16;
     const cd* b2 = u2k + (g2 < n2 ? g2 : 0);
 #pragma unroll
@@ -320,12 +325,19 @@ __global__ __launch_bounds__(kRhoWaves * 64) void drho_mfma_kernel(
       bic[s] = b.y;
     }
   };
+  // the wave's run of tiles is walked row by row: (it, jt) advance together
+  // with t, so no tile index is divided out
+  int it = t0 / njt, jt = t0 - (t0 / njt) * njt;
   int cur = -1;
-  if (NBS > 0 && t0 < t1) fetch_b(t0);
+  if (NBS > 0 && t0 < t1) fetch_b(jt);
   for (int t = t0; t < t1; ++t) {
-    const int it = t / njt, jt = t - it * njt;
     const int g1 = it * 16 + l16, g2 = jt * 16 + l16;  // this lane's A row and B column
     const bool ok1 = g1 < n1, ok2 = g2 < n2;
+    int in = it, jn = jt + 1;
+    if (jn == njt) {
+      jn = 0;
+      ++in;
+    }
     mf64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
     if (NBS > 0) {
       if (it != cur) {
@@ -334,20 +346,28 @@ __global__ __launch_bounds__(kRhoWaves * 64) void drho_mfma_kernel(
         for (int s = 0; s < NR; ++s) {
           const int nu = 4 * s + kq;
           const cd a = a1[(long)(nu < nbnd ? nu : 0) * npwx1];
-          arc[s] = nu < nbnd ? a.x : 0.0;
-          aic[s] = nu < nbnd ? -a.y : 0.0;  // conj(u1); rows past the sphere are never binned
+          arc[s] = nu < nbnd ? f * a.x : 0.0;
+          aic[s] = nu < nbnd ? -f * a.y : 0.0;  // f conj(u1); rows past the sphere are never binned
+          naic[s] = -aic[s];
+        }
+        // box offsets of this row's G1 (rows past the sphere get a bin
+        // outside the box)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gr = it * 16 + 4 * r + kq;
+          o1v[r] = gr < n1 ? o1s[gr] : INT_MIN / 2;
         }
         cur = it;
       }
 #pragma unroll
       for (int s = 0; s < NR; ++s) {
         cr = mfma_16x16x4(arc[s], brc[s], cr);
-        cr = mfma_16x16x4(-aic[s], bic[s], cr);
+        cr = mfma_16x16x4(naic[s], bic[s], cr);
         ci = mfma_16x16x4(arc[s], bic[s], ci);
         ci = mfma_16x16x4(aic[s], brc[s], ci);
       }
       // the next tile's B loads run under this tile's binning
-      if (t + 1 < t1) fetch_b(t + 1);
+      if (t + 1 < t1) fetch_b(jn);
     } else {
       const cd* a1 = u1k + (ok1 ? g1 : 0);
       const cd* b2 = u2k + (ok2 ? g2 : 0);
@@ -364,24 +384,27 @@ __global__ __launch_bounds__(kRhoWaves * 64) void drho_mfma_kernel(
         ci = mfma_16x16x4(ar, b.y, ci);
         ci = mfma_16x16x4(ai, b.x, ci);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = it * 16 + 4 * r + kq;
+        o1v[r] = gr < n1 ? o1s[gr] : INT_MIN / 2;
+      }
     }
     // this lane's results: G1 rows 4 r + kq of the tile, G2 column l16
-    if (!ok2) continue;
-    const int c2 = o2s[g2] - base;
-    int o1v[4];
+    if (ok2) {
+      const int c2 = o2s[g2] - base;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int gr = it * 16 + 4 * r + kq;
-      o1v[r] = o1s[gr < n1 ? gr : 0];
+      for (int r = 0; r < 4; ++r) {
+        const int bin = c2 - o1v[r];
+        // past the sphere, or another x-slice of the box
+        if ((unsigned)bin < (unsigned)nbin) {
+          atomicAdd(&bre[bin], fb * cr[r]);
+          atomicAdd(&bim[bin], fb * ci[r]);
+        }
+      }
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int gr = it * 16 + 4 * r + kq;
-      const int bin = c2 - o1v[r];
-      if (gr >= n1 || bin < 0 || bin >= nbin) continue;  // past the sphere, or another x-slice of the box
-      atomicAdd(&bre[bin], f * cr[r]);
-      atomicAdd(&bim[bin], f * ci[r]);
-    }
+    it = in;
+    jt = jn;
   }
   __syncthreads();
   cd* dst = part + ((long)k * D1 + x0) * D2 * D3;
