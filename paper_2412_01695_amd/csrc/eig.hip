@@ -15,7 +15,9 @@
 //      eight lanes per eigenvalue);
 //   4. eigenvectors of T_r by inverse iteration, Gaussian elimination with
 //      partial pivoting on T_r - lambda (one lane each, from a fixed
-//      pseudo-random start), then Gram-Schmidt (twice) within each cluster of
+//      pseudo-random start, two solves: with lambda accurate to rounding each
+//      solve shrinks the components along the other eigenvectors by their
+//      gap over that error), then Gram-Schmidt (twice) within each cluster of
 //      eigenvalues closer than 1e-3 of the matrix norm;
 //   5. back through D and the reflectors: x = H_0 (... H_{n-3} (D y)), four
 //      eigenvectors per wave at once.
@@ -43,14 +45,32 @@ constexpr int kEigYs = kEigMax + 1;
 constexpr int kEigNev = 32;   // most eigenpairs returned
 constexpr int kEigThreads = 512;             // one workgroup per k-point
 constexpr int kEigWaves = kEigThreads / 64;
-constexpr int kEigPQ = kEigThreads / 64;     // work-items per row of p = g A u
+constexpr int kEigPQ = 8;                    // work-items per row of the reduction (one DPP group)
+static_assert(kEigPQ * kEigMax <= kEigThreads, "one row of the trailing block per group of kEigPQ");
 
-__device__ __forceinline__ double wave_sum64(double v) { return wave_sum(v); }
+// v on lane l of a wave, read into a wave-uniform value (l uniform)
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
 
-// 1/x for the Sturm recurrence and the inverse iteration: the hardware
-// reciprocal estimate refined by two Newton-Raphson steps r <- r + r (1 - x r)
-// (each step squares the relative error), a few dependent operations instead
-// of a full IEEE division
+// sum over the 64 lanes of a wave (every lane active), the same value on every
+// lane: DPP sums within the rows of 16 lanes, then the four row sums read from
+// lanes 0, 16, 32 and 48 (register reads, no LDS round trip)
+__device__ __forceinline__ double wave_sum64(double v) {
+  v += dpp<0xB1>(v);   // quad_perm 1,0,3,2
+  v += dpp<0x4E>(v);   // quad_perm 2,3,0,1
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+// 1/x for the reflectors and the inverse iteration: the hardware reciprocal
+// estimate (relative error up to about 5e-8) refined by two Newton-Raphson
+// steps r <- r + r (1 - x r) (each squares the relative error; measured to
+// within rounding after the second), a few dependent operations instead of a
+// full IEEE division
 __device__ __forceinline__ double rcp_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
   r = fma(r, fma(-x, r, 1.0), r);
@@ -58,23 +78,25 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return r;
 }
 
-// Householder reflector of a column held one component per lane (x on lane
-// l < mm, zero beyond): H = I - g u u^H with H x = beta e_0, beta = -e^{i arg
-// x_0} |x|, u = x - beta e_0; g = 0 (no reflection, beta = x_0) when x has
-// nothing below its first component.  Called by a whole wave.
-__device__ __forceinline__ void make_reflector(cd x, int mm, int lane, double& g, cd& beta, cd& u) {
-  const double sig = wave_sum64(lane >= 1 && lane < mm ? x.x * x.x + x.y * x.y : 0.0);
-  const double ar = __shfl(x.x, 0, 64), ai = __shfl(x.y, 0, 64);
+// Householder reflector of a column held one component per lane, x_0 on lane
+// h (h uniform), the rest on lanes h+1 .. mm-1, anything on the other lanes
+// ignored: H = I - g u u^H with H x = beta e_0, beta = -e^{i arg x_0} |x|,
+// u = x - beta e_0 (u on the same lanes as x); g = 0 (no reflection, beta =
+// x_0) when x has nothing below its first component.  Called by a whole wave.
+__device__ __forceinline__ void make_reflector(cd x, int h, int mm, int lane, double& g, cd& beta, cd& u) {
+  const double sig = wave_sum64(lane > h && lane < mm ? x.x * x.x + x.y * x.y : 0.0);
+  const double ar = lane_value(x.x, h), ai = lane_value(x.y, h);
   g = 0.0;
   beta = {ar, ai};
   u = x;
   if (sig > 0.0) {
     const double amag = sqrt(ar * ar + ai * ai);
     const double xn = sqrt(amag * amag + sig);
-    beta = amag > 0.0 ? cd{-xn * ar / amag, -xn * ai / amag} : cd{-xn, 0.0};
+    const double xa = amag > 0.0 ? xn * rcp_nr(amag) : 0.0;
+    beta = amag > 0.0 ? cd{-xa * ar, -xa * ai} : cd{-xn, 0.0};
     const cd u0 = {ar - beta.x, ai - beta.y};
-    g = 2.0 / (u0.x * u0.x + u0.y * u0.y + sig);
-    if (lane == 0) u = u0;
+    g = 2.0 * rcp_nr(u0.x * u0.x + u0.y * u0.y + sig);
+    if (lane == h) u = u0;
   }
 }
 
@@ -92,9 +114,11 @@ constexpr int kEigPacked = kEigMax * (kEigMax + 1) / 2;
 struct EigLds {
   cd ecx[kEigMax];                         // complex subdiagonal of T
   cd ph[kEigMax];                          // phases D
-  cd pw[kEigMax];                          // p, then w of the current reflector
+  cd pw[kEigMax];                          // p of the current reflector
+  cd uu[2][kEigMax];                       // u of reflector j in uu[j & 1], by row of A
   double g[kEigMax];                       // reflector factors g_j
   double d[kEigMax], e[kEigMax];           // T_r
+  double e2[kEigMax];                      // e_i^2 for the Sturm counts
   double lam[kEigNev];
   int cstart[kEigNev];                     // first index of each eigenvalue's cluster
   double scal[4];
@@ -140,8 +164,11 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
     if (lane < n - 1) x = A[pk(1 + lane, 0)];
     double g0;
     cd beta, u;
-    make_reflector(x, n - 1, lane, g0, beta, u);
-    if (lane < n - 1) A[pk(1 + lane, 0)] = u;
+    make_reflector(x, 0, n - 1, lane, g0, beta, u);
+    if (lane < n - 1) {
+      A[pk(1 + lane, 0)] = u;
+      S.uu[0][1 + lane] = u;
+    }
     if (lane == 0) {
       S.g[0] = g0;
       S.ecx[0] = beta;
@@ -151,26 +178,50 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;  // trailing size, 2 .. 63
     const double gj = S.g[j];  // uniform
+    // row r of the trailing block on the eight work-items q of one lane group,
+    // the last rows on wave 0, which forms the next reflector meanwhile and so
+    // takes no rows of the update below once the block is 56 rows or fewer
+    const int r = (kEigThreads / kEigPQ - 1) - (tid >> 3), q = tid & 7;
+    const cd* uj = S.uu[j & 1];
     if (gj != 0.0) {
-      // p_r = g sum_l A[j+1+r][j+1+l] u_l, four work-items per row
-      const int r = tid / kEigPQ, q = tid % kEigPQ;
+      // p_r = g sum_l A[j+1+r][j+1+l] u_l: each work-item takes l = q + 8 s,
+      // in two batches of four whose loads are issued before their products
       cd acc = {0.0, 0.0};
       if (r < m) {
-        const int i = j + 1 + r;
-        for (int l = q; l < m; l += kEigPQ) {
-          // A[i][c] from the lower triangle, conjugated above the diagonal
-          const int c = j + 1 + l;
-          const cd al = c <= i ? A[pk(i, c)] : A[pk(c, i)];
-          const cd a = {al.x, c <= i ? al.y : -al.y}, u = A[pk(c, j)];
-          acc.x += a.x * u.x - a.y * u.y;
-          acc.y += a.x * u.y + a.y * u.x;
+        const int i = j + 1 + r, ri = pk(i, 0);
+#pragma unroll
+        for (int h = 0; h < kEigMax / kEigPQ; h += 4) {
+          if (q + kEigPQ * h >= m) break;  // nothing left in this row
+          cd av[4], uv[4];
+          // packed offset of row c, stepped along with c (no multiply per entry)
+          int c = j + 1 + q + kEigPQ * h, rc = pk(c, 0);
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) {
+            // A[i][c] from the lower triangle, conjugated above the diagonal;
+            // past the block (c >= n) the diagonal entry, multiplied by u = 0
+            av[s2] = A[c <= i ? ri + c : (c < n ? rc + i : ri + i)];
+            uv[s2] = uj[c < n ? c : n - 1];
+            rc += kEigPQ * c + kEigPQ * (kEigPQ + 1) / 2;
+            c += kEigPQ;
+          }
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) {
+            const int l = q + kEigPQ * (h + s2);
+            const int c = j + 1 + l;
+            const cd a = {av[s2].x, c <= i ? av[s2].y : -av[s2].y};
+            const cd u = l < m ? uv[s2] : cd{0.0, 0.0};
+            acc.x += a.x * u.x - a.y * u.y;
+            acc.y += a.x * u.y + a.y * u.x;
+          }
         }
       }
-#pragma unroll
-      for (int o = 1; o < kEigPQ; o <<= 1) {
-        acc.x += __shfl_xor(acc.x, o, 64);
-        acc.y += __shfl_xor(acc.y, o, 64);
-      }
+      // sum over the eight work-items of the row (DPP within groups of 8)
+      acc.x += dpp<0xB1>(acc.x);
+      acc.y += dpp<0xB1>(acc.y);
+      acc.x += dpp<0x4E>(acc.x);
+      acc.y += dpp<0x4E>(acc.y);
+      acc.x += dpp<0x141>(acc.x);
+      acc.y += dpp<0x141>(acc.y);
       if (r < m && q == 0) S.pw[r] = {gj * acc.x, gj * acc.y};
     }
     __syncthreads();
@@ -180,7 +231,7 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
       cd p = {0.0, 0.0}, u = {0.0, 0.0};
       if (lane < m) {
         p = S.pw[lane];
-        u = A[pk(j + 1 + lane, j)];
+        u = uj[j + 1 + lane];
       }
       kk = 0.5 * gj * wave_sum64(u.x * p.x + u.y * p.y);
     }
@@ -189,7 +240,7 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
       cd a = {0.0, 0.0};
       if (lane < m) a = A[pk(j + 1 + lane, j + 1)];
       if (gj != 0.0 && lane < m) {
-        const cd ur = A[pk(j + 1 + lane, j)], u0 = A[pk(j + 1, j)];
+        const cd ur = uj[j + 1 + lane], u0 = uj[j + 1];
         const cd pr = S.pw[lane], p0 = S.pw[0];
         const cd wr = {pr.x - kk * ur.x, pr.y - kk * ur.y}, w0 = {p0.x - kk * u0.x, p0.y - kk * u0.y};
         // a -= u_r conj(w_0) + w_r conj(u_0)
@@ -198,14 +249,14 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
       }
       cd st = a;  // value stored at row j+1+lane of column j+1
       if (j + 3 < n) {
-        // reflector of column j+1 from rows j+2 .. n-1: component lane+1 on lane
-        cd x = {__shfl(a.x, lane + 1 < 64 ? lane + 1 : 63, 64), __shfl(a.y, lane + 1 < 64 ? lane + 1 : 63, 64)};
-        if (lane >= m - 1) x = {0.0, 0.0};
+        // reflector of column j+1 from rows j+2 .. n-1, in place on lanes 1 .. m-1
         double g1;
         cd beta, u;
-        make_reflector(x, m - 1, lane, g1, beta, u);
-        const cd ub = {__shfl(u.x, lane > 0 ? lane - 1 : 0, 64), __shfl(u.y, lane > 0 ? lane - 1 : 0, 64)};
-        if (lane >= 1) st = ub;
+        make_reflector(a, 1, m, lane, g1, beta, u);
+        if (lane >= 1) {
+          st = u;
+          if (lane < m) S.uu[(j + 1) & 1][j + 1 + lane] = u;
+        }
         if (lane == 0) {
           S.g[j + 1] = g1;
           S.ecx[j + 1] = beta;
@@ -213,20 +264,35 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
       }
       if (lane < m) A[pk(j + 1 + lane, j + 1)] = st;
     }
-    if (gj != 0.0) {
+    if (gj != 0.0 && r >= 1 && r < m) {
       // the rest of the trailing block (columns j+2 .., lower triangle):
-      // A -= u w^H + w u^H
-      const int mc = m - 1;
-      for (int e = tid; e < m * mc; e += kEigThreads) {
-        const int r = e / mc, l = 1 + e - (e / mc) * mc;
-        if (l > r) continue;
-        const cd ur = A[pk(j + 1 + r, j)], ul = A[pk(j + 1 + l, j)];
-        const cd pr = S.pw[r], pl = S.pw[l];
-        const cd wr = {pr.x - kk * ur.x, pr.y - kk * ur.y}, wl = {pl.x - kk * ul.x, pl.y - kk * ul.y};
-        cd& av = A[pk(j + 1 + r, j + 1 + l)];
-        // u_r conj(w_l) + w_r conj(u_l)
-        av.x -= ur.x * wl.x + ur.y * wl.y + wr.x * ul.x + wr.y * ul.y;
-        av.y -= ur.y * wl.x - ur.x * wl.y + wr.y * ul.x - wr.x * ul.y;
+      // A -= u w^H + w u^H; row r, columns l = 1 + q + 8 s <= r, in batches
+      // of four whose loads are issued before their stores
+      const cd ur = uj[j + 1 + r], pr = S.pw[r];
+      const cd wr = {pr.x - kk * ur.x, pr.y - kk * ur.y};
+#pragma unroll
+      for (int h = 0; h < kEigMax / kEigPQ; h += 4) {
+        if (1 + q + kEigPQ * h > r) break;  // nothing left in this row
+        cd ul[4], pl[4], av[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int l = 1 + q + kEigPQ * (h + s2), lc = l <= r ? l : 1;
+          ul[s2] = uj[j + 1 + lc];
+          pl[s2] = S.pw[lc];
+          av[s2] = A[pk(j + 1 + r, j + 1 + lc)];
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int l = 1 + q + kEigPQ * (h + s2);
+          if (l <= r) {
+            const cd wl = {pl[s2].x - kk * ul[s2].x, pl[s2].y - kk * ul[s2].y};
+            cd a = av[s2];
+            // u_r conj(w_l) + w_r conj(u_l)
+            a.x -= ur.x * wl.x + ur.y * wl.y + wr.x * ul[s2].x + wr.y * ul[s2].y;
+            a.y -= ur.y * wl.x - ur.x * wl.y + wr.y * ul[s2].x - wr.x * ul[s2].y;
+            A[pk(j + 1 + r, j + 1 + l)] = a;
+          }
+        }
       }
     }
     __syncthreads();
@@ -255,6 +321,7 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
     if (i < n) S.d[i] = di;
     if (i + 1 < n) {
       S.e[i] = mag;
+      S.e2[i] = mag * mag;
       S.ph[i + 1] = p;
     }
     if (i == 0) S.ph[0] = {1.0, 0.0};
@@ -297,9 +364,14 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
         double qa = S.d[0] - xa;
         if (fabs(qa) < pivmin) qa = -pivmin;
         ca += qa < 0.0;
+#pragma unroll 8
         for (int i = 1; i < n; ++i) {
-          const double di = S.d[i], e2 = S.e[i - 1] * S.e[i - 1];
-          qa = (di - xa) - e2 * rcp_nr(qa);
+          // 1/q from the hardware estimate and one Newton-Raphson step
+          // (relative error about 2e-15): the count is that of T_r with its
+          // e_i^2 perturbed at that level
+          double rq = __builtin_amdgcn_rcp(qa);
+          rq = fma(rq, fma(-qa, rq, 1.0), rq);
+          qa = (S.d[i] - xa) - S.e2[i - 1] * rq;
           if (fabs(qa) < pivmin) qa = -pivmin;
           ca += qa < 0.0;
         }
@@ -338,36 +410,33 @@ __global__ __launch_bounds__(kEigThreads) void heevx_kernel(const cd* __restrict
         h ^= h << 5;
         y[i] = (double)(h & 0xFFFFFF) / 8388608.0 - 1.0;
       }
-      for (int iter = 0; iter < 3; ++iter) {
+      for (int iter = 0; iter < 2; ++iter) {
         // forward elimination with partial pivoting, right-hand side y
         double c0 = S.d[0] - lm, c1 = n > 1 ? S.e[0] : 0.0, rc = y[0];
         unsigned long long swapped = 0;
+#pragma unroll 4
         for (int i = 0; i + 1 < n; ++i) {
           const double s = S.e[i], dd = S.d[i + 1] - lm, ee = i + 2 < n ? S.e[i + 1] : 0.0, b1 = y[i + 1];
-          if (fabs(c0) >= fabs(s)) {
-            const double l = c0 != 0.0 ? s * rcp_nr(c0) : 0.0;
-            u0[i] = c0;
-            u1[i] = c1;
-            y[i] = rc;
-            c0 = dd - l * c1;
-            c1 = ee;
-            rc = b1 - l * rc;
-          } else {
-            const double l = c0 * rcp_nr(s);
-            u0[i] = s;
-            u1[i] = dd;
-            swapped |= 1ull << i;  // third row entry ee
-            y[i] = b1;
-            const double n0 = c1 - l * dd;
-            c1 = -l * ee;
-            c0 = n0;
-            rc = rc - l * b1;
-          }
+          // pivot row: the current one, or row i+1 (swapped: its third
+          // entry ee is the implied u2); one reciprocal either way and no
+          // divergent branch between the two cases
+          const bool sw = !(fabs(c0) >= fabs(s));
+          const double piv = sw ? s : c0, oth = sw ? c0 : s;
+          const double l = piv != 0.0 ? oth * rcp_nr(piv) : 0.0;
+          u0[i] = piv;
+          u1[i] = sw ? dd : c1;
+          y[i] = sw ? b1 : rc;
+          if (sw) swapped |= 1ull << i;
+          const double c0n = sw ? c1 - l * dd : dd - l * c1;
+          c1 = sw ? -l * ee : ee;
+          rc = sw ? rc - l * b1 : b1 - l * rc;
+          c0 = c0n;
         }
         u0[n - 1] = c0;
         y[n - 1] = rc;
         // back substitution (tiny pivots replaced by eps |T|), then normalise
         double y1 = 0.0, y2 = 0.0, ss = 0.0;
+#pragma unroll 4
         for (int i = n - 1; i >= 0; --i) {
           double piv = u0[i];
           if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
