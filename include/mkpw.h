@@ -17,6 +17,14 @@
  *   |k+G|^2, ties by Miller index (m1, m2, m3) lexicographically; see
  *   pw_get_miller) followed by npwx - npw[k] padding entries that must be
  *   zero on input and are written as zero on output.
+ *   The set-up calls (pw_set_lattice, pw_set_cutoff, pw_set_kpoints,
+ *   pw_set_vloc, pw_set_projectors, pw_set_qij) take host arrays only and
+ *   copy them to the device once: the potential, the projector rows and the
+ *   D and q coefficients are inputs of the crystal, not of each call.  The
+ *   per-call vectors (wavefunctions, H|psi>, right-hand sides, solutions,
+ *   induced densities) are device memory; the small per-k arrays
+ *   (eigenvalues, shifts, weights, iteration counts) and the perturbing
+ *   potential of pw_dfpt_rhs are host arrays, as each entry point states.
  *   Device pointers are HIP device memory owned by the caller (e.g. torch
  *   tensors); the library never frees or reallocates them.  All device work
  *   is ordered on the context's stream; calls return once the work is
