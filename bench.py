@@ -466,28 +466,22 @@ def dfpt_q_sample(torch, mkpw, cfg_id):
         sk.close()
 
 
-def serving_sample(n, rate=20.0):
-    from paper_2412_01695_amd import serve
-    reqs = serve.make_requests(n, rate)
-    serve.prewarm(reqs)
-    srv = serve.Server(0, 8)
-    # start-up: a few requests of the same distribution (another seed) tune the
-    # H|psi> launch shapes before traffic arrives
-    warm = serve.make_requests(48, rate, seed=7)
-    serve.prewarm(warm)
-    t = time.monotonic()
-    bad = srv.warmup(warm)
-    progress(f"serving: start-up warm-up of {len(warm)} requests in {time.monotonic() - t:.1f} s"
-             f"{'' if not bad else f' ({len(bad)} failed)'}")
-    t = time.monotonic()
-    serve.replay(reqs, srv, report=lambda n: progress(f"serving: {n} requests submitted"))
-    wall = time.monotonic() - t
-    srv.close()
-    out = serve.summarize(reqs, wall)
-    out["stream"] = (f"{n} Poisson arrivals at {rate:g}/s: nk U{{16..1024}}, ecut U[20,45] Ry, nbnd U{{8..32}}, "
-                     f"1-2 atoms; mixed precision refined to 1e-6 Ry; 8 slots, 64 GiB HBM budget; server "
-                     f"warmed up with {len(warm)} requests of another seed (launch shapes tuned)")
-    return out
+def serving_sample(n, rate=20.0, timeout_s=900):
+    """The serving stream in a server process of its own (the serve module's
+    entry point): the measurement is that of a server that has done nothing
+    else, and a failure there is reported here instead of ending this run."""
+    import subprocess
+    cmd = [sys.executable, "-u", "-m", "paper_2412_01695_amd.serve", "--requests", str(n), "--rate", str(rate)]
+    try:
+        p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=None, cwd=os.path.dirname(os.path.abspath(__file__)),
+                           timeout=timeout_s, text=True)
+    except subprocess.TimeoutExpired:
+        return {"error": f"server process did not finish within {timeout_s} s", "command": " ".join(cmd[1:])}
+    lines = [x for x in p.stdout.splitlines() if x.startswith("{")]
+    if p.returncode != 0 or not lines:
+        how = f"signal {-p.returncode}" if p.returncode < 0 else f"exit code {p.returncode}"
+        return {"error": f"server process ended with {how}", "command": " ".join(cmd[1:])}
+    return json.loads(lines[-1])
 
 
 def hpsi_sample(torch, mkpw, cid, steps, warmup):
@@ -702,7 +696,10 @@ def main():
         progress("DFPT q != 0 done")
     if args.serve_requests > 0:
         res["serving"] = serving_sample(args.serve_requests)
-        progress(f"serving: p50 {res['serving']['p50_s']:.3f} s, p99 {res['serving']['p99_s']:.3f} s")
+        if "error" in res["serving"]:
+            progress(f"serving: {res['serving']['error']}")
+        else:
+            progress(f"serving: p50 {res['serving']['p50_s']:.3f} s, p99 {res['serving']['p99_s']:.3f} s")
     print(json.dumps(res))
 
 

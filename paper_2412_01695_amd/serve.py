@@ -23,6 +23,7 @@ import argparse
 import collections
 import json
 import math
+import sys
 import threading
 import time
 
@@ -33,25 +34,11 @@ from . import mkpw, synth
 _VLOC_CACHE = {}
 _VLOC_LOCK = threading.Lock()
 
-# host threads for the projector tables of a request (numpy releases the
-# interpreter lock in the array work, so the chunks run in parallel)
-_BETA_POOL = None
-_BETA_POOL_LOCK = threading.Lock()
-
-
-def _beta_pool():
-    global _BETA_POOL
-    with _BETA_POOL_LOCK:
-        if _BETA_POOL is None:
-            from concurrent.futures import ThreadPoolExecutor
-            _BETA_POOL = ThreadPoolExecutor(max_workers=8, thread_name_prefix="beta")
-        return _BETA_POOL
-
-
 def projector_table(cfg, npw, npwx, mall, kchunk=128):
     """beta_p(k+G) in the library's (nk, nproj, npwx) layout, zero padded, from
     the concatenated Miller indices of every k (library order), built in
-    chunks of k-points on host threads."""
+    chunks of k-points (one vectorised evaluation per chunk, in the calling
+    thread)."""
     beta = np.zeros((cfg.nk, cfg.nproj, npwx), dtype=np.complex128)
     off = np.concatenate([[0], np.cumsum(npw)]).astype(np.int64)
     b = synth.reciprocal_rows(cfg.lat)
@@ -65,7 +52,8 @@ def projector_table(cfg, npw, npwx, mall, kchunk=128):
         pos = np.arange(m.shape[0]) - np.repeat(off[k0:k1] - off[k0], n)
         beta[k0 + kl, :, pos] = synth.beta_values(cfg, q).T
 
-    list(_beta_pool().map(chunk, range(0, cfg.nk, kchunk)))
+    for k0 in range(0, cfg.nk, kchunk):
+        chunk(k0)
     return beta
 
 
@@ -312,18 +300,34 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--warmup", type=int, default=48, help="start-up requests (another seed) before the stream")
     args = ap.parse_args()
+
+    def progress(msg):
+        print(f"[serve {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
     reqs = make_requests(args.requests, args.rate)
     prewarm(reqs)
     srv = Server(0, args.slots, int(args.budget_gb * (1 << 30)))
+    bad = []
     if args.warmup > 0:
+        # start-up: requests of the same distribution (another seed) tune the
+        # H|psi> launch shapes before traffic arrives
         warm = make_requests(args.warmup, args.rate, seed=7)
         prewarm(warm)
-        srv.warmup(warm)
+        t = time.monotonic()
+        bad = srv.warmup(warm)
+        progress(f"start-up warm-up of {len(warm)} requests in {time.monotonic() - t:.1f} s"
+                 f"{'' if not bad else f' ({len(bad)} failed)'}")
     t = time.monotonic()
-    replay(reqs, srv)
+    replay(reqs, srv, report=lambda n: progress(f"{n} requests submitted"))
     wall = time.monotonic() - t
     srv.close()
-    print(json.dumps(summarize(reqs, wall)))
+    out = summarize(reqs, wall)
+    out["warmup_failed"] = len(bad)
+    out["stream"] = (f"{args.requests} Poisson arrivals at {args.rate:g}/s: nk U{{16..1024}}, ecut U[20,45] Ry, "
+                     f"nbnd U{{8..32}}, 1-2 atoms; mixed precision refined to 1e-6 Ry; {args.slots} slots, "
+                     f"{args.budget_gb:g} GiB HBM budget; server warmed up with {args.warmup} requests of "
+                     f"another seed (launch shapes tuned); one server process")
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

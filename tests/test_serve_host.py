@@ -30,3 +30,14 @@ def test_projector_table_matches_per_k_construction():
             assert np.all(got[:, :, npwx - 1][np.asarray(npw) < npwx] == 0)
         finally:
             mkpw.pw_destroy(ctx)
+
+
+def test_bench_serving_sample_reports_instead_of_raising():
+    """The bench runs the serving stream in a server process of its own: a
+    server that cannot run (here: no GPU) comes back as an error entry, and a
+    server that can comes back with its latency summary; neither raises."""
+    import bench
+
+    out = bench.serving_sample(2, timeout_s=300)
+    assert isinstance(out, dict)
+    assert ("error" in out and "command" in out) or ("p50_s" in out and out["requests"] == 2)
