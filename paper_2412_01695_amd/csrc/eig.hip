@@ -553,41 +553,50 @@ __global__ __launch_bounds__(64) void chol_inv_kernel(const cd* __restrict__ Sg,
     dmax = m;
   }
   __syncthreads();
+  // right-looking: column j is final once the updates of the columns before it
+  // are in; it is scaled, then the trailing lower triangle takes its rank-1
+  // update, lane (row parity, column) = (tid / 32, tid % 32)
+  const int cl = tid & 31, rp = tid >> 5;
   for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      double d = L[j][j].x;
-      for (int q = 0; q < j; ++q) d -= L[j][q].x * L[j][q].x + L[j][q].y * L[j][q].y;
-      if (!(d > 1e-12 * dmax)) bad = 1;
-      L[j][j] = {sqrt(fmax(d, 1e-300)), 0.0};
-    }
+    const double d = L[j][j].x;
+    if (tid == 0 && !(d > 1e-12 * dmax)) bad = 1;
+    const double piv = sqrt(fmax(d, 1e-300)), inv = 1.0 / piv;
+    for (int i = j + 1 + tid; i < n; i += 64) L[i][j] = {L[i][j].x * inv, L[i][j].y * inv};
+    if (tid == 0) L[j][j] = {piv, 0.0};
     __syncthreads();
-    for (int i = j + 1 + tid; i < n; i += 64) {
-      double xr = L[i][j].x, xi = L[i][j].y;
-      for (int q = 0; q < j; ++q) {  // - L[i][q] conj(L[j][q])
-        cd a = L[i][q], b = L[j][q];
-        xr -= a.x * b.x + a.y * b.y;
-        xi -= a.y * b.x - a.x * b.y;
+    const int c = j + 1 + cl;
+    if (c < n) {
+      const cd lc = L[c][j];
+      for (int i = c + rp; i < n; i += 2) {  // L[i][c] -= L[i][j] conj(L[c][j])
+        const cd a = L[i][j];
+        L[i][c].x -= a.x * lc.x + a.y * lc.y;
+        L[i][c].y -= a.y * lc.x - a.x * lc.y;
       }
-      double inv = 1.0 / L[j][j].x;
-      L[i][j] = {xr * inv, xi * inv};
     }
     __syncthreads();
   }
-  // columns of L^-1 by forward substitution, one column per work-item
-  for (int c = tid; c < n; c += 64) {
-    for (int i = 0; i < n; ++i) Li[i][c] = {0.0, 0.0};
-    for (int i = c; i < n; ++i) {
-      double xr = (i == c) ? 1.0 : 0.0, xi = 0.0;
-      for (int q = c; q < i; ++q) {
-        cd a = L[i][q], b = Li[q][c];
-        xr -= a.x * b.x - a.y * b.y;
-        xi -= a.x * b.y + a.y * b.x;
-      }
-      double inv = 1.0 / L[i][i].x;
-      Li[i][c] = {xr * inv, xi * inv};
-    }
+  // L^-1 row by row, right-looking: row q is final once the rows above have
+  // been subtracted; it is scaled by 1/L_qq, then subtracted from the rows
+  // below (Li starts as the identity; only c <= row is ever nonzero)
+  for (int e = tid; e < n * kCholMax; e += 64) {
+    const int i = e / kCholMax, cc = e - (e / kCholMax) * kCholMax;
+    Li[i][cc] = {i == cc ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
+  for (int q = 0; q < n; ++q) {
+    const double inv = 1.0 / L[q][q].x;
+    if (tid <= q) Li[q][tid] = {Li[q][tid].x * inv, Li[q][tid].y * inv};
+    __syncthreads();
+    if (cl <= q) {
+      const cd lq = Li[q][cl];
+      for (int i = q + 1 + rp; i < n; i += 2) {  // Li[i][c] -= L[i][q] Li[q][c]
+        const cd a = L[i][q];
+        Li[i][cl].x -= a.x * lq.x - a.y * lq.y;
+        Li[i][cl].y -= a.x * lq.y + a.y * lq.x;
+      }
+    }
+    __syncthreads();
+  }
   cd* M = Mg + (long)k * m_kstride;
   for (int e = tid; e < n * n; e += 64) {
     int i = e / n, j = e % n;  // M = Li^H (upper triangular)
