@@ -159,6 +159,12 @@ __global__ __launch_bounds__(256) void rows_combine_mfma_kernel(CombArgs a) {
 
 // ------------------------------------------------------------------ in-place Y <- Y M, M upper triangular
 
+// n <= NB rows of Y per k (NB a multiple of 8, at most 32): a work-item owns
+// one column g of the rows; row i is read once and added into the outputs
+// j >= i it feeds (Y_j = sum_{i <= j} Y_i M_ij, outputs in registers), both
+// loops unrolled so that only the triangle is formed; every row is read
+// before the first is written
+template <int NB>
 __global__ __launch_bounds__(256) void rows_trmm_kernel(c64d* Yb, long y_kstride, const int* y_off, const int* y_cnt,
                                                         int npwx, const c64d* Mb, long m_kstride, int ldm) {
   const int k = blockIdx.y;
@@ -167,29 +173,30 @@ __global__ __launch_bounds__(256) void rows_trmm_kernel(c64d* Yb, long y_kstride
   const int g = blockIdx.x * 256 + threadIdx.x;
   c64d* Y = Yb + (long)k * y_kstride + (long)y_off[k] * npwx;
   const c64d* M = Mb + (long)k * m_kstride;
-  __shared__ c64d ms[32 * 32];
-  for (int e = threadIdx.x; e < n * n; e += 256) ms[e] = M[(long)(e / n) * ldm + (e % n)];
+  __shared__ c64d ms[NB * NB];
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e - (e / NB) * NB;
+    ms[e] = i < n && j < n ? M[(long)i * ldm + j] : c64d{0.0, 0.0};
+  }
   __syncthreads();
   if (g >= npwx) return;
-  // each row of this work-item's column is read once and added into the
-  // outputs it feeds (Y_j = sum_{i <= j} Y_i M_ij, outputs in registers)
-  constexpr int kMax = 32;
-  double ar[kMax], ai[kMax];
+  double ar[NB], ai[NB];
 #pragma unroll
-  for (int j = 0; j < kMax; ++j) ar[j] = ai[j] = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const c64d x = Y[(long)i * npwx + g];
+  for (int j = 0; j < NB; ++j) ar[j] = ai[j] = 0.0;
 #pragma unroll
-    for (int j = 0; j < kMax; ++j) {
-      if (j >= i && j < n) {
-        const c64d c = ms[i * n + j];
+  for (int i = 0; i < NB; ++i) {
+    if (i < n) {
+      const c64d x = Y[(long)i * npwx + g];
+#pragma unroll
+      for (int j = i; j < NB; ++j) {
+        const c64d c = ms[i * NB + j];
         ar[j] += x.x * c.x - x.y * c.y;
         ai[j] += x.x * c.y + x.y * c.x;
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < kMax; ++j)
+  for (int j = 0; j < NB; ++j)
     if (j < n) Y[(long)j * npwx + g] = {ar[j], ai[j]};
 }
 
@@ -240,9 +247,19 @@ pw_status launch_combine(pw_ctx* c, const CombArgs& a, int ni_max, hipStream_t s
 
 pw_status launch_trmm(pw_ctx* c, cplx<double>* Y, long y_kstride, const int* y_off, const int* y_cnt,
                       const cplx<double>* M, long m_kstride, int ldm, hipStream_t st) {
+  // the row counts y_cnt are at most ldm (the order of M)
+  if (ldm < 1 || ldm > 32) return set_err(c, PW_EINVAL, "triangular factor larger than 32");
   dim3 grid((c->npwx + 255) / 256, c->nk);
-  hipLaunchKernelGGL(rows_trmm_kernel, grid, dim3(256), 0, st, Y, y_kstride, y_off, y_cnt, c->npwx, M, m_kstride,
-                     ldm);
+#define MKPW_TRMM(NB)                                                                                          \
+  hipLaunchKernelGGL(rows_trmm_kernel<NB>, grid, dim3(256), 0, st, Y, y_kstride, y_off, y_cnt, c->npwx, M, m_kstride, \
+                     ldm)
+  switch ((ldm + 7) / 8) {
+    case 1: MKPW_TRMM(8); break;
+    case 2: MKPW_TRMM(16); break;
+    case 3: MKPW_TRMM(24); break;
+    default: MKPW_TRMM(32); break;
+  }
+#undef MKPW_TRMM
   return check_launch(c, "rows_trmm", st);
 }
 
