@@ -477,6 +477,8 @@ def serving_sample(n, rate=20.0, timeout_s=900):
                            timeout=timeout_s, text=True)
     except subprocess.TimeoutExpired:
         return {"error": f"server process did not finish within {timeout_s} s", "command": " ".join(cmd[1:])}
+    except OSError as e:
+        return {"error": f"server process could not be started: {e}", "command": " ".join(cmd[1:])}
     lines = [x for x in p.stdout.splitlines() if x.startswith("{")]
     if p.returncode != 0 or not lines:
         how = f"signal {-p.returncode}" if p.returncode < 0 else f"exit code {p.returncode}"
