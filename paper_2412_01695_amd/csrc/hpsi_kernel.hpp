@@ -931,10 +931,13 @@ pw_status launch_one(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, 
   return launch_shape<T, N, WC>(c, sel, psi, hpsi, st, sh);
 }
 
-// Window capacities built for an N^3 mesh: every other value from about N/3
-// to N/2 + 2 (the usual range of the wave-function window on a density-sized
-// mesh), then N.  A launch takes the smallest one that holds the window, so
-// at most one padded input per line is transformed.
+// Window capacities built for an N^3 mesh: one below the first rung, then
+// every other value from about N/3 to N/2 + 2 (the usual range of the
+// wave-function window on a density-sized mesh), then N.  A launch takes the
+// smallest one that holds the window, so at most one padded input per line is
+// transformed, and none at the lowest rungs, where the window of a
+// density-sized mesh most often falls (a padded input of the x convolution
+// costs 2 WC - 1 of its WC^2 multiply-adds).
 template <int N>
 constexpr int wc_first() {
   return (N + 2) / 3 > 5 ? (N + 2) / 3 : 5;
@@ -959,6 +962,10 @@ pw_status launch_ladder(pw_ctx* c, int w, const VecSel& sel, const void* psi, vo
 template <class T, int N>
 pw_status launch_n(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi, hipStream_t st, void* vscratch) {
   const int w = std::max(c->wx, std::max(c->wy, c->wz));
+  constexpr int W0 = wc_first<N>() - 1;
+  if constexpr (W0 >= 5) {
+    if (w <= W0) return launch_one<T, N, W0>(c, sel, psi, hpsi, st, vscratch);
+  }
   return launch_ladder<T, N, wc_first<N>()>(c, w, sel, psi, hpsi, st, vscratch);
 }
 
