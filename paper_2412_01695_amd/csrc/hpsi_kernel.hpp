@@ -437,10 +437,12 @@ __global__ __launch_bounds__(NT) void hpsi_kernel(KTables t, VecSel sel, int npr
       // from xt[l3][d + WC - 1][l2]; a work-item owns one line, in place
       constexpr int DW = 2 * WC - 1;
       // the compact x convolution holds about 100 fewer registers; it is the
-      // faster one in FP32, and it keeps the 1024-work-item kernels from
-      // spilling, while the FP64 ones at 256 and 512 work-items run faster
-      // with every tap loaded up front
-      constexpr bool XCOMPACT = sizeof(T) == 4 || NT >= 1024;
+      // faster one in FP32 and in the FP64 kernels of 512 work-items (36^3,
+      // capacity 11: 4.09 against 4.16 ms on 1728 k), and it keeps the
+      // 1024-work-item kernels from spilling, while the FP64 ones at 256
+      // work-items run faster with every tap loaded up front (30^3: 1.91
+      // against 1.94 ms on 2048 k)
+      constexpr bool XCOMPACT = sizeof(T) == 4 || NT >= 512;
       const cplx<T>* xt = reinterpret_cast<const cplx<T>*>(vr);
       for (int i = tid; i < N * nl; i += NT) {
         const int lcn = i / N, l2 = i - lcn * N;
