@@ -62,15 +62,29 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramArgs a) {
   // share of the chunk but forms no products
   const bool live = i0 + 16 * ti < ni && j0 + 16 * tj < nj;
   mf64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
-  for (int g0 = 0; g0 < npw; g0 += kMK) {
+  // the next chunk's loads are issued into registers before this chunk's
+  // products, so their latency is hidden behind the matrix cores
+  constexpr int kQ = kMB * kMK / 256;
+  c64d pa[kQ], pb[kQ];
+  auto fetch = [&](int g0) {
 #pragma unroll
-    for (int q = 0; q < kMB * kMK / 256; ++q) {
+    for (int q = 0; q < kQ; ++q) {
       const int e = tid + q * 256, r = e / kMK, g = e % kMK;
       const bool gok = g0 + g < npw;
-      As[r][g] = gok && i0 + r < ni ? A[(long)(i0 + r) * a.ld + g0 + g] : c64d{0.0, 0.0};
-      Bs[r][g] = gok && j0 + r < nj ? B[(long)(j0 + r) * a.ld + g0 + g] : c64d{0.0, 0.0};
+      pa[q] = gok && i0 + r < ni ? A[(long)(i0 + r) * a.ld + g0 + g] : c64d{0.0, 0.0};
+      pb[q] = gok && j0 + r < nj ? B[(long)(j0 + r) * a.ld + g0 + g] : c64d{0.0, 0.0};
+    }
+  };
+  fetch(0);
+  for (int g0 = 0; g0 < npw; g0 += kMK) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int e = tid + q * 256, r = e / kMK, g = e % kMK;
+      As[r][g] = pa[q];
+      Bs[r][g] = pb[q];
     }
     __syncthreads();
+    if (g0 + kMK < npw) fetch(g0 + kMK);
 #pragma unroll
     for (int kk = 0; kk < kMK && live; kk += 4) {
       const c64d x = As[16 * ti + l16][kk + kq], y = Bs[16 * tj + l16][kk + kq];
@@ -135,15 +149,25 @@ __global__ __launch_bounds__(256) void rows_combine_mfma_kernel(CombArgs a) {
     }
     __syncthreads();
     mf64x4 dr = {0.0, 0.0, 0.0, 0.0}, di = {0.0, 0.0, 0.0, 0.0};
-    for (int i0 = 0; i0 < ni; i0 += 4) {
-      const int i = i0 + kq;
-      // A = C^T (row: output j = l16, column: input i = kq); B = X (row i, column g)
-      const c64d c = cs[i][l16];
-      const c64d x = gok && i < ni ? X[(long)i * npwx + g] : c64d{0.0, 0.0};
-      dr = mfma4(c.x, x.x, dr);
-      dr = mfma4(-c.y, x.y, dr);
-      di = mfma4(c.x, x.y, di);
-      di = mfma4(c.y, x.x, di);
+    // four steps of four input rows at a time, their X loads issued first
+    // (rows past ni read row 0 and meet a zero C entry)
+    for (int i0 = 0; i0 < ni; i0 += 16) {
+      c64d xs[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 4 * u + kq;
+        xs[u] = gok ? X[(long)(i < ni ? i : 0) * npwx + g] : c64d{0.0, 0.0};
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (i0 + 4 * u >= ni) break;
+        // A = C^T (row: output j = l16, column: input i); B = X (row i, column g)
+        const c64d c = cs[i0 + 4 * u + kq][l16];
+        dr = mfma4(c.x, xs[u].x, dr);
+        dr = mfma4(-c.y, xs[u].y, dr);
+        di = mfma4(c.x, xs[u].y, di);
+        di = mfma4(c.y, xs[u].x, di);
+      }
     }
     if (!gok) continue;
 #pragma unroll
