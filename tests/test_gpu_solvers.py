@@ -217,6 +217,28 @@ def test_davidson_small_basis_restarts():
     assert max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref) < TOL_FP64_HA
 
 
+def test_davidson_refuses_dependent_starting_vectors():
+    """Two equal starting vectors at one k: the block orthonormalisation meets
+    a singular overlap (a Cholesky pivot below 1e-12 of the largest) and the
+    solve is refused with PW_EINVAL naming that k; a solve from independent
+    vectors on the same context then succeeds."""
+    from paper_2412_01695_amd import mkpw
+    cfg = synth.make_config(1)
+    torch, s = _system(cfg)
+    g = np.array(s.psi_guess(cfg.nbnd))
+    g[2, 5] = g[2, 1]
+    psi = to_dev(torch, g)
+    with pytest.raises(mkpw.PwError) as e:
+        mkpw.pw_davidson(s.ctx, mkpw.PW_FP64, cfg.nbnd, psi, s.nk, 1e-10, 300)
+    torch.cuda.synchronize()
+    assert e.value.status == mkpw.PW_EINVAL
+    assert "linearly dependent" in str(e.value) and "at k 2" in str(e.value)
+    st, eig, iters, conv, psi = _davidson(torch, s, 0, 1e-10)
+    assert st == 0 and conv.all()
+    ref = _oracle_eigs(cfg, s, range(cfg.nk), cfg.nbnd)
+    assert max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref) < TOL_FP64_HA
+
+
 def test_davidson_noconv_flags():
     from paper_2412_01695_amd import mkpw
     cfg = synth.make_config(1)
