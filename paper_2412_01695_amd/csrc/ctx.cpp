@@ -221,6 +221,29 @@ pw_status upload(pw_ctx* c, const T* host, size_t count, T** dev) {
 
 extern "C" {
 
+namespace {
+// The solvers' work buffers are stream-ordered allocations from the device's
+// default memory pool.  With the pool's default release threshold (0) its
+// memory goes back to the system at every synchronisation, so each call maps
+// its buffers anew; keeping up to an eighth of the device (at most 32 GiB)
+// cached lets repeated calls reuse them.  Set once per device and process.
+void keep_pool_memory(int device) {
+  static std::mutex mu;
+  static std::vector<int> done;
+  std::lock_guard<std::mutex> lk(mu);
+  if (std::find(done.begin(), done.end(), device) != done.end()) return;
+  done.push_back(device);
+  hipMemPool_t pool = nullptr;
+  size_t free_b = 0, total_b = 0;
+  if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess || hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  uint64_t keep = std::min<uint64_t>((uint64_t)total_b / 8, (uint64_t)32 << 30);
+  if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) (void)hipGetLastError();
+}
+}  // namespace
+
 pw_status pw_create(pw_ctx** out, int hip_device, void* hip_stream) {
   if (!out) return PW_EINVAL;
   *out = nullptr;
@@ -239,6 +262,7 @@ pw_status pw_create(pw_ctx** out, int hip_device, void* hip_stream) {
       delete c;
       return PW_EDEVICE;
     }
+    keep_pool_memory(hip_device);
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
     } else {
