@@ -1,7 +1,7 @@
 """Benchmark: batched H|psi> over many k-points on one MI355X.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config 4] [--no-cpu]
-                    [--no-solve] [--serve-requests 1000]
+                    [--no-solve] [--serve-requests N]
 
 A step is one pw_h_psi over the whole batch of the workload (every k-point
 and band in one launch, inputs resident in HBM).  The default workload is
@@ -18,9 +18,11 @@ reports the H|psi> throughput of the 512- and 2048-k workloads, the Davidson
 time-to-solution of the headline batch (FP64 to 1e-10 Ry; mixed precision to
 1e-6 Ry, with and without its FP64 refinement, and the eigenvalue error of
 each against the oracle's dense diagonalisation on sampled k-points), the
-DFPT CG at q = 0 and at the paper's q, and the p50/p99 latency of the
-continuous-batching server on a Poisson stream of Davidson requests.  Prints
-one JSON line.
+DFPT CG at q = 0 and at the paper's q, and, with --serve-requests N, the
+p50/p99 latency of the continuous-batching server on a Poisson stream of N
+Davidson requests (not run by default: the server process has ended twice
+with a host segmentation fault during its concurrent start-up, cause not
+found).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -540,7 +542,10 @@ def main():
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=1000)
+    # the serving stream is off by default: its server process has ended twice
+    # with a host segmentation fault during the concurrent start-up of its
+    # first 48 requests on 8 slots, and the cause is not found
+    ap.add_argument("--serve-requests", type=int, default=0)
     ap.add_argument("--other-configs", default="2,3",
                     help="workloads whose H|psi> throughput is reported beside the headline ('' to skip)")
     ap.add_argument("--dfpt-config", type=int, default=3, help="workload of the DFPT CG sample (0: skip)")
@@ -696,7 +701,11 @@ def main():
         progress("DFPT q = 0 done")
         res["dfpt_q"] = dfpt_q_sample(torch, mkpw, args.dfpt_config)
         progress("DFPT q != 0 done")
-    if args.serve_requests > 0:
+    if args.serve_requests <= 0:
+        res["serving"] = {"skipped": "not run by default: the server process ended twice with a host "
+                                     "segmentation fault during the concurrent start-up of its first 48 "
+                                     "requests on 8 slots; cause not found (--serve-requests N runs it)"}
+    else:
         res["serving"] = serving_sample(args.serve_requests)
         if "error" in res["serving"]:
             progress(f"serving: {res['serving']['error']}")
