@@ -51,7 +51,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("hpsi_kernel.hpp", "fft.hpp", "hpsi_types.hpp", "wave.hpp")
 MEASURED_TRAFFIC = {
     ("fcc1-ecut40-fft36-1728k", "fp64", (4, 512, 14)): {
-        "sources": "e6f84b559b6dec24", "fetch_kib": 185567.0, "write_kib": 331776.0,
+        "sources": "f7c8de6240b6b685", "fetch_kib": 185567.0, "write_kib": 331776.0,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "profile": "profiles/hpsi_fp64_fcc1-ecut40-fft36-1728k.md"},
 }

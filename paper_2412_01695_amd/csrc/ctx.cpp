@@ -87,14 +87,36 @@ void dev_free(pw_ctx* c, void* p) {
   }
 }
 
+// Every query or change of a kernel's attributes in the process goes through
+// this lock: contexts on several host threads tune and launch at once.
+std::mutex g_attr_mu;
+std::unordered_map<const void*, size_t> g_lds_limit;                  // dynamic LDS allowed per kernel
+std::unordered_map<const void*, std::pair<int, size_t>> g_resources;  // registers, scratch bytes per lane
+
+bool kernel_resources(const void* kernel, int* regs, size_t* scratch) {
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  auto it = g_resources.find(kernel);
+  if (it == g_resources.end()) {
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, kernel) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    it = g_resources.emplace(kernel, std::make_pair(a.numRegs, a.localSizeBytes)).first;
+  }
+  *regs = it->second.first;
+  *scratch = it->second.second;
+  return true;
+}
+
 pw_status ensure_lds_limit(pw_ctx* c, const void* kernel, size_t lds) {
   // Raise a kernel's dynamic-LDS limit to the CU's 160 KiB once per process,
-  // under a lock and before the first launch of that kernel, so that no
-  // thread changes a kernel's attributes while another thread launches it.
-  static std::mutex mu;
-  static std::unordered_map<const void*, size_t> limit;  // dynamic LDS allowed per kernel
+  // under the attribute lock and before the first launch of that kernel, so
+  // that no thread changes a kernel's attributes while another thread
+  // launches it or reads them.
   if (lds <= 64 * 1024) return PW_OK;
-  std::lock_guard<std::mutex> lk(mu);
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  auto& limit = g_lds_limit;
   auto it = limit.find(kernel);
   if (it == limit.end()) {
     hipFuncAttributes fa;

@@ -764,13 +764,11 @@ pw_status launch_shape(pw_ctx* c, const VecSel& sel, const void* psi, void* hpsi
 // VGPRs per lane, allocated in blocks of 8); 0 if the kernel spills registers
 // to scratch memory (left out of the autotuning).
 inline int wgs_by_vgpr(const void* kern, int threads) {
-  hipFuncAttributes a{};
-  if (hipFuncGetAttributes(&a, kern) != hipSuccess || a.numRegs <= 0) {
-    (void)hipGetLastError();
-    return 1;
-  }
-  if (a.localSizeBytes > 0) return 0;
-  const int v = (a.numRegs + 7) / 8 * 8;
+  int regs = 0;
+  size_t scratch = 0;
+  if (!kernel_resources(kern, &regs, &scratch) || regs <= 0) return 1;
+  if (scratch > 0) return 0;
+  const int v = (regs + 7) / 8 * 8;
   const int waves_per_simd = std::min(8, 512 / v);
   return std::max(1, waves_per_simd * 4 / (threads / 64));
 }

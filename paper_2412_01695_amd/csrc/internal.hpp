@@ -181,6 +181,9 @@ pw_status launch_spsi(pw_ctx* c, pw_prec prec, const VecSel& sel, const void* ps
 pw_status check_launch(pw_ctx* c, const char* what, hipStream_t st);
 // thread-safe, once-per-kernel raise of the dynamic LDS limit (needed above 64 KiB)
 pw_status ensure_lds_limit(pw_ctx* c, const void* kernel, size_t lds);
+// a kernel's registers per lane and scratch bytes per lane, read once per
+// process under the lock that also covers ensure_lds_limit; false on failure
+bool kernel_resources(const void* kernel, int* regs, size_t* scratch);
 pw_status launch_gram(pw_ctx* c, const GramArgs& a, int ni_max, int nj_max, hipStream_t st);
 pw_status launch_combine(pw_ctx* c, const CombArgs& a, int ni_max, hipStream_t st);
 pw_status launch_trmm(pw_ctx* c, cplx<double>* Y, long y_kstride, const int* y_off, const int* y_cnt,
