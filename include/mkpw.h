@@ -97,6 +97,9 @@ const char* pw_last_error(const pw_ctx* ctx);
  * one by one; the results are the same), "mixed_refine" (default 1: the
  * PW_MIXED Davidson refines in FP64 after its complex64 phase; 0: it returns
  * the complex64-phase result, for measuring what the refinement adds),
+ * "mixed_switch_rtol_e7" (default 2000, in [100, 100000]: the residual norm,
+ * in units of 1e-7, below which a band counts as converged in the PW_MIXED
+ * Davidson's complex64 phase; the FP64 phase uses 1e-5),
  * "cg_switch_digits" (default 10, in [2, 20]: the PW_MIXED CG leaves complex64
  * once every system's |rho| has fallen by 10^-digits from its start),
  * "dav_nconv" (default 0 = all: pw_davidson declares a k converged once its
@@ -220,7 +223,7 @@ pw_status pw_s_psi(pw_ctx* ctx, pw_prec prec, int nbnd, const void* psi, void* s
  * iters, converged: host (nk) ints, may be NULL.
  * PW_MIXED applies H in complex64 until every band's eigenvalue changes by
  * less than max(tol_ry/2, 2e-6) Ha with residual norm below 2e-4 (what an
- * FP32 H application resolves), then refines with H in FP64 to the FP64
+ * FP32 H application resolves; option "mixed_switch_rtol_e7"), then refines with H in FP64 to the FP64
  * criterion above (option "mixed_refine" = 0 stops after the complex64 phase).
  * Every per-iteration decision (which bands get a correction, restarts,
  * dropped blocks) is taken on the device; the host only learns, one iteration

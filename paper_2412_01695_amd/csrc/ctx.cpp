@@ -350,6 +350,9 @@ pw_status pw_set_option(pw_ctx* c, const char* key, int64_t value) {
     c->solver_graph = value != 0;
   } else if (k == "mixed_refine") {
     c->mixed_refine = value != 0;
+  } else if (k == "mixed_switch_rtol_e7") {
+    if (value < 100 || value > 100000) return set_err(c, PW_EINVAL, "mixed_switch_rtol_e7 must be in [100, 100000]");
+    c->mixed_switch_rtol_e7 = value;
   } else if (k == "dav_nconv") {
     if (value < 0 || value > 1024) return set_err(c, PW_EINVAL, "dav_nconv must be in [0, 1024]");
     c->dav_nconv = value;
@@ -377,6 +380,7 @@ pw_status pw_get_option(const pw_ctx* c, const char* key, int64_t* value) {
   else if (k == "tune_log") *value = c->tune_log;
   else if (k == "solver_graph") *value = c->solver_graph;
   else if (k == "mixed_refine") *value = c->mixed_refine;
+  else if (k == "mixed_switch_rtol_e7") *value = c->mixed_switch_rtol_e7;
   else if (k == "cg_switch_digits") *value = c->cg_switch_digits;
   else if (k == "dav_nconv") *value = c->dav_nconv;
   else if (k == "last_iterations") *value = c->last_iterations;

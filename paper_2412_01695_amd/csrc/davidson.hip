@@ -303,7 +303,7 @@ pw_status davidson_run(pw_ctx* c, pw_prec prec, int nbnd, cd* psi, double* eig, 
   const int nbmax = std::min<int>((int)c->dav_basis_factor * nbnd, 64);
   const double tol = 0.5 * tol_ry;  // Ha
   const double rtol64 = 1e-5;
-  const double tol32 = std::max(tol, 2e-6), rtol32 = 2e-4;
+  const double tol32 = std::max(tol, 2e-6), rtol32 = 1e-7 * (double)c->mixed_switch_rtol_e7;
   const int nconv = c->dav_nconv > 0 && c->dav_nconv < nbnd ? (int)c->dav_nconv : nbnd;
   const bool gen = c->have_q;  // generalized problem: S != 1
   c->last_iterations = c->last_hpsi_kbands = c->last_graph_replays = 0;

@@ -94,6 +94,7 @@ struct pw_ctx {
   int64_t tune_log = 0;      // print the autotuning timings to stderr
   int64_t solver_graph = 1;  // replay one solver iteration as a captured HIP graph
   int64_t mixed_refine = 1;  // mixed-precision Davidson: refine in FP64 after the complex64 phase
+  int64_t mixed_switch_rtol_e7 = 2000;  // mixed Davidson: residual norm ending the complex64 phase, 1e-7 units
   int64_t cg_switch_digits = 10;  // mixed-precision CG: leave complex64 once |rho| fell by 10^-digits
   int64_t dav_nconv = 0;          // Davidson: bands that must converge (0: all; the rest are buffer bands)
   // statistics of the last solver call: iterations run, and k-band rows H was

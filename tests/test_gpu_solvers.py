@@ -122,22 +122,27 @@ def test_davidson_buffer_bands():
 
 def test_davidson_mixed_before_and_after_refinement():
     # the complex64 phase alone stops near what an FP32 H application resolves;
-    # the FP64 refinement brings every eigenvalue within 1e-6 Ry of the oracle
+    # the FP64 refinement brings every eigenvalue within 1e-6 Ry of the oracle.
+    # A Ritz value is within its residual norm of an eigenvalue, so a complex64
+    # phase that ends at residual 2e-5 (option mixed_switch_rtol_e7 = 200)
+    # leaves errors below 2e-5 Ha
     from paper_2412_01695_amd import mkpw
     cfg0 = synth.make_config(4)
     cfg = synth.subset(cfg0, np.arange(0, cfg0.nk, 96))
     torch, s = _system(cfg)
     ref = _oracle_eigs(cfg, s, range(cfg.nk), cfg.nbnd)
     errs = {}
-    for refine in (0, 1):
+    for refine, rt in ((0, 2000), (1, 2000), (0, 200)):
         mkpw.pw_set_option(s.ctx, "mixed_refine", refine)
+        mkpw.pw_set_option(s.ctx, "mixed_switch_rtol_e7", rt)
         st, eig, iters, conv, psi = _davidson(torch, s, 1, 1e-6)
         assert st == 0 and conv.all()
-        errs[refine] = max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref)
-        print("refine", refine, "max |eig err| Ha", errs[refine], "iters", iters.min(), iters.max(),
-              "H k-bands", mkpw.pw_get_option(s.ctx, "last_hpsi_kbands"))
-    assert errs[1] < TOL_MIXED_HA
-    assert errs[0] < 1e-4
+        errs[refine, rt] = max(np.max(np.abs(eig[ik] - ref[ik])) for ik in ref)
+        print("refine", refine, "switch residual", rt * 1e-7, "max |eig err| Ha", errs[refine, rt],
+              "iters", iters.min(), iters.max(), "H k-bands", mkpw.pw_get_option(s.ctx, "last_hpsi_kbands"))
+    assert errs[1, 2000] < TOL_MIXED_HA
+    assert errs[0, 2000] < 2e-4
+    assert errs[0, 200] < 2e-5
 
 
 @pytest.mark.parametrize("prec", [0, 1])

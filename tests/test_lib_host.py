@@ -158,7 +158,8 @@ def test_shape_options(mk):
     ctx = mk.pw_create(-1, None)
     for key, good, bad in (("hpsi_variant", (0, 1, 2, 3, 4, 5), (-1, 6)), ("hpsi_threads", (0, 256, 512, 1024), (128, 300)),
                            ("hpsi_slab", (0, 1, 36), (-1, 513)), ("tune_log", (0, 1), ()),
-                           ("cg_switch_digits", (2, 10, 20), (1, 21)), ("dav_nconv", (0, 8, 1024), (-1, 1025))):
+                           ("cg_switch_digits", (2, 10, 20), (1, 21)), ("dav_nconv", (0, 8, 1024), (-1, 1025)),
+                           ("mixed_switch_rtol_e7", (100, 2000, 100000), (99, 100001))):
         for v in good:
             mk.pw_set_option(ctx, key, v)
             assert mk.pw_get_option(ctx, key) == v
@@ -166,6 +167,9 @@ def test_shape_options(mk):
             with pytest.raises(mk.PwError) as e:
                 mk.pw_set_option(ctx, key, v)
             assert e.value.status == mk.PW_EINVAL
+    ctx2 = mk.pw_create(-1, None)
+    assert mk.pw_get_option(ctx2, "mixed_switch_rtol_e7") == 2000  # default: residual 2e-4
+    mk.pw_destroy(ctx2)
     for key in ("hpsi_variant_tuned", "hpsi_slab_tuned", "hpsi_threads_tuned"):
         assert mk.pw_get_option(ctx, key) == 0  # nothing launched yet
     mk.pw_destroy(ctx)
