@@ -15,9 +15,11 @@ HIP events on the launch stream.  The CPU baseline is the FP64 oracle's
 dense route (H_k psi_k by zgemm per k, H_k built outside the timed region),
 on a process pool over the host cores.  Beside the step throughput it
 reports the H|psi> throughput of the 512- and 2048-k workloads, the Davidson
-time-to-solution of the headline batch (FP64 to 1e-10 Ry; mixed precision to
-1e-6 Ry, with and without its FP64 refinement, and the eigenvalue error of
-each against the oracle's dense diagonalisation on sampled k-points), the
+time-to-solution of the headline batch (FP64 to 1e-10 and to 1e-6 Ry; mixed
+precision to 1e-6 Ry, with and without its FP64 refinement; for each, the
+largest eigenvalue difference over all k against the FP64 1e-10 Ry solve and
+the error against the oracle's dense diagonalisation on sampled k-points,
+the sample holding each solve's worst k), the
 DFPT CG at q = 0 and at the paper's q, and, with --serve-requests N, the
 p50/p99 latency of the continuous-batching server on a Poisson stream of N
 Davidson requests (not run by default: the server process has ended twice
