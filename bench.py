@@ -56,6 +56,10 @@ MEASURED_TRAFFIC = {
         "sources": "f7c8de6240b6b685", "fetch_kib": 185567.0, "write_kib": 331776.0,
         "fetch_scale": 2.0, "write_scale": 1.0,
         "profile": "profiles/hpsi_fp64_fcc1-ecut40-fft36-1728k.md"},
+    ("fcc1-ecut40-fft36-1728k", "mixed", (5, 512, 8)): {
+        "sources": "f7c8de6240b6b685", "fetch_kib": 96364.5, "write_kib": 165888.0,
+        "fetch_scale": 2.0, "write_scale": 1.0,
+        "profile": "profiles/hpsi_mixed_fcc1-ecut40-fft36-1728k.md"},
 }
 
 
@@ -662,7 +666,9 @@ def main():
         res["mixed"] = {"value": nkb / (out["mixed"] * 1e-3), "ms_per_step": out["mixed"], "dtype": "c64",
                         "shape": shapes["mixed"],
                         "speedup_vs_fp64": out["fp64"] / out["mixed"],
-                        "roofline_frac": flops_launch / (out["mixed"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+                        "roofline_frac": flops_launch / (out["mixed"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                        "traffic": measured_traffic(cfg.name, "mixed", shapes["mixed"]),
+                        "io_bytes_per_launch": io32_kb * nkb}
     eigs = {}
     if not args.no_solve:
         solve = {}
